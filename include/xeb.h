@@ -1,0 +1,244 @@
+/*
+ * xeb.h — C ABI of the MI355X (gfx950) multi-tensor contraction library.
+ *
+ * The library computes the amplitudes <s_i|C|0^n> of a quantum circuit C for a
+ * whole batch of bitstrings s_1..s_k by one sliced contraction of the circuit's
+ * tensor network, reusing every sub-contraction that several strings (and
+ * several slices) share, and reduces them to the linear XEB fidelity.
+ *
+ * Paper: Kalachev, Panteleev, Yung, "Multi-Tensor Contraction for XEB
+ * Verification of Quantum Circuits" (arXiv 2108.05665).
+ *   - amplitudes as contractions of per-string networks: section
+ *     "Multi-batch simulator";
+ *   - reuse of shared sub-expressions, lexicographic tuple order, one cached
+ *     entry per subtree: section "Multi-tensor contraction algorithm" and
+ *     Appendix C (procedures eval_all / eval');
+ *   - pairwise contraction cost 2^(q+r): Appendix A; slicing: Appendix A,
+ *     paragraph "Slicing";
+ *   - linear XEB: Eq. (1) of the Introduction.
+ *
+ * Conventions for every call:
+ *   - Every call returns an int: XEB_OK (0) or a negative error code.  No call
+ *     throws across the ABI.  xeb_last_error() returns a thread-local message
+ *     describing the last failure on the calling thread.
+ *   - Handles are opaque.  The caller owns every buffer it passes; the plan
+ *     owns its host-side schedule; device memory for the plan's tables comes
+ *     from the caller (xeb_plan_bind_workspace).
+ *   - Pointers named "host" point to host memory, "dev" to device memory on
+ *     the plan's device.  A hipStream_t is passed as void* (NULL = the null
+ *     stream).
+ *   - Calls on one plan must be ordered: the plan keeps which slice's tables
+ *     are resident, so two xeb_contract calls on one plan must not run
+ *     concurrently and must use streams ordered with each other.
+ */
+#ifndef XEB_H
+#define XEB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define XEB_OK 0
+#define XEB_EINVAL (-1)  /* bad argument: circuit, tree, slice list, range, sizes */
+#define XEB_ENOMEM (-2)  /* host allocation failed, or workspace too small / over budget */
+#define XEB_EHIP (-3)    /* HIP runtime error; the message carries HIP's text */
+#define XEB_ESTATE (-4)  /* call out of order (e.g. contract before bind) */
+
+/* Opaque plan handle. */
+typedef struct xeb_plan* xeb_plan_t;
+
+/* ---- precision of the contraction kernels ------------------------------ */
+#define XEB_PREC_C64 0         /* complex64, FP32 MFMA, FP32 accumulation */
+#define XEB_PREC_SPLIT_FP16 1  /* reserved: hi/lo FP16 operands, FP32 accumulation */
+#define XEB_PREC_SPLIT_BF16 2  /* reserved: hi/lo BF16 operands, FP32 accumulation */
+
+/*
+ * A circuit: gates in time order.
+ *   gate_qubits (host) int32 [n_gates][2]: the qubits of gate g; column 1 is -1
+ *     for a one-qubit gate.  The two qubits of a two-qubit gate differ.
+ *   gate_mats (host) double [n_gates][32]: (re, im) pairs.  A two-qubit gate is
+ *     a 4x4 row-major matrix U[out][in] with basis index 2*b_q0 + b_q1; a
+ *     one-qubit gate uses the first 4 complex entries as a 2x2 row-major
+ *     matrix U[out][in] (the rest is ignored).
+ *   1 <= n_qubits <= 64.
+ */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_gates;
+  const int32_t* gate_qubits;
+  const double* gate_mats;
+} xeb_circuit_t;
+
+/*
+ * A binary contraction tree (section "Tensor network contraction": leaves are
+ * the tensors, internal nodes the pairwise contractions).
+ *   Node ids: 0..n_leaves-1 are the network's leaves (xeb_network_describe
+ *   order); internal node n_leaves+i has children children[2i], children[2i+1],
+ *   both ids smaller than n_leaves+i.  Every node except the last (the root)
+ *   is the child of exactly one internal node.  n_leaves >= 1; children may be
+ *   NULL when n_leaves == 1.
+ *   The left child is the first of the pair; variables are ordered as they
+ *   occur in the tree, left first (Appendix C).
+ */
+typedef struct {
+  int32_t n_leaves;
+  const int32_t* children; /* host, int32 [n_leaves-1][2] */
+} xeb_tree_t;
+
+typedef struct {
+  int32_t fuse_1q;        /* 1: fuse one-qubit gates into two-qubit gates (default 1) */
+  int32_t fold_kets;      /* 1: project |0> into the first gate on each qubit (default 1) */
+  int32_t precision;      /* XEB_PREC_* (default XEB_PREC_C64) */
+  int32_t device;         /* HIP device ordinal of the plan (default 0) */
+  uint64_t memory_budget; /* max workspace bytes, 0 = unlimited (default 0) */
+  int32_t trace;          /* >0: print one JSON line per node at plan creation */
+  int32_t force_generic;  /* 1: use the generic per-element kernel for every node */
+} xeb_options_t;
+
+typedef struct {
+  int64_t n_leaves;
+  int64_t n_internal;
+  int64_t k;                 /* strings passed, duplicates included */
+  int64_t k_distinct;        /* distinct strings */
+  int32_t n_qubits;
+  int32_t n_sliced;          /* s; the plan has 2^s slices */
+  int64_t sum_variants;      /* sum over internal nodes of |t_T| (string variants) */
+  int64_t max_tensor_elems;  /* largest tensor per variant (after slicing), elements */
+  double cmacs_per_slice;    /* sum_T |t_T| 2^(q_T+r_T): one evaluation of every node */
+  double cmacs_full;         /* complex MACs for all 2^s slices under the plan's schedule */
+  double rw_elems_full;      /* elements read+written by all contractions, all slices */
+  double evals_full;         /* node evaluations (kernel launches) for all slices */
+  uint64_t workspace_bytes;
+} xeb_stats_t;
+
+#define XEB_KERNEL_GENERIC 0  /* per-element kernel (small or sparse nodes) */
+#define XEB_KERNEL_MFMA 1     /* FP32-MFMA stacked GEMM */
+
+typedef struct {
+  int32_t left, right;       /* child node ids */
+  int64_t variants;          /* |t_T|: distinct string keys of this node */
+  int64_t left_variants, right_variants;
+  int32_t m_bits, n_bits, k_bits; /* free legs of left, free legs of right, shared legs */
+  uint64_t slice_mask;       /* bit j set: the node depends on sliced leg j */
+  int32_t kernel;            /* XEB_KERNEL_* */
+  int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
+  double cmacs_per_eval;     /* |t_T| 2^(q+r) */
+} xeb_node_stats_t;
+
+/* Fill *opt with the defaults listed above. */
+void xeb_options_default(xeb_options_t* opt);
+
+/* Thread-local text of the last error (never NULL). */
+const char* xeb_last_error(void);
+
+/*
+ * The tensor network of a circuit (section "Multi-batch simulator"), host only,
+ * no device needed.  Convention, shared with any independent implementation:
+ *  1. Fusion (fuse_1q): walk the gates with a pending one-qubit product P_q per
+ *     qubit; a one-qubit gate U on q sets P_q := U P_q; a two-qubit gate W on
+ *     (a, b) is emitted as W (P_a (x) P_b) and clears P_a, P_b.  Afterwards each
+ *     qubit q with pending P_q (ascending q) left-multiplies it into the last
+ *     emitted two-qubit gate touching q (on q's side), or, if none touches q,
+ *     is emitted as a one-qubit gate.  Without fusion the gates are emitted as
+ *     given.
+ *  2. Leaves: ket leaves first (ascending qubit), then one leaf per emitted
+ *     gate.  With fold_kets a ket leaf exists only for a qubit no emitted gate
+ *     touches; the others are projected onto |0> inside their first gate.
+ *  3. Legs are wire segments in creation order: ket segments, then per emitted
+ *     gate one output segment per qubit (first qubit's, then second's).
+ *  4. A gate leaf's legs: its input segments (a folded input is absent), then
+ *     its output segments.  The last segment of each qubit is its open output
+ *     leg; it is fixed by that qubit's bit of the string.
+ * Outputs (host, any may be NULL to query sizes first):
+ *   *n_leaves, *n_legs, *n_leaf_legs (total entries of leaf_legs);
+ *   leaf_leg_offsets int32 [n_leaves+1] (CSR offsets into leaf_legs);
+ *   leaf_legs int32 [n_leaf_legs];
+ *   leg_qubit int32 [n_legs]: q if the leg is qubit q's output leg, else -1.
+ * Errors: XEB_EINVAL for a malformed circuit.
+ */
+int xeb_network_describe(const xeb_circuit_t* circuit, int32_t fuse_1q, int32_t fold_kets,
+                         int32_t* n_leaves, int32_t* n_legs, int32_t* n_leaf_legs,
+                         int32_t* leaf_leg_offsets, int32_t* leaf_legs, int32_t* leg_qubit);
+
+/*
+ * Compile a plan (host only; no device memory is touched until bind).
+ *   bitstrings (host) uint64 [k]: bit q = qubit q; duplicates allowed (each
+ *     occurrence receives the amplitude).  k >= 0; bits at or above n_qubits
+ *     must be zero.
+ *   contraction_tree: over the leaves of xeb_network_describe(circuit,
+ *     opt->fuse_1q, opt->fold_kets).
+ *   sliced_legs (host) int32 [s]: distinct internal (non-output) leg ids; slice
+ *     id sigma fixes leg sliced_legs[j] to bit j of sigma (Appendix A,
+ *     "Slicing").  0 <= s <= 40.  May be NULL when s == 0.
+ *   opt: NULL for defaults.
+ * The plan dedupes the strings, orders every node's variants in the
+ * lexicographic order of Appendix C, precomputes gather maps, picks a kernel
+ * per node, sizes its device workspace by a dry run (Appendix C, "emulation
+ * mode") and builds the leaf tensors in FP64 before rounding them to the
+ * kernel precision.
+ * Errors: XEB_EINVAL (malformed input), XEB_ENOMEM (host memory, or the
+ * workspace exceeds opt->memory_budget).
+ */
+int xeb_plan_create(const xeb_circuit_t* circuit, const uint64_t* bitstrings, int64_t k,
+                    const xeb_tree_t* contraction_tree, const int32_t* sliced_legs, int32_t s,
+                    const xeb_options_t* opt, xeb_plan_t* out);
+
+/* Device bytes the plan needs (from the dry run). */
+int xeb_plan_workspace_bytes(xeb_plan_t plan, uint64_t* bytes);
+
+/*
+ * Give the plan its device workspace: dev_ptr (device, 256-byte aligned, at
+ * least xeb_plan_workspace_bytes) stays owned by the caller and must outlive
+ * the plan's use.  Uploads the leaf tables and gather maps (synchronous).
+ * Rebinding is allowed; it invalidates resident tables.
+ * Errors: XEB_EINVAL (NULL or misaligned), XEB_ENOMEM (too small), XEB_EHIP.
+ */
+int xeb_plan_bind_workspace(xeb_plan_t plan, void* dev_ptr, uint64_t bytes);
+
+/*
+ * Contract slices [slice_begin, slice_end) (0 <= begin <= end <= 2^s) and add
+ * each string's sum over those slices into amps.
+ *   amps (device) complex128 [k] ((re, im) doubles), in the order of the
+ *     bitstrings passed to xeb_plan_create; zero it before the first call.
+ *     Each call adds its slices' partial amplitudes (FP32 complex results of
+ *     the contraction, widened to FP64) in increasing slice order with
+ *     Neumaier compensation and folds the compensation into amps at the end
+ *     of the call, so results are deterministic for a given split of the
+ *     slice range.  Repeated calls accumulate; the full amplitude needs the
+ *     calls to cover [0, 2^s) exactly once.
+ *   stream: hipStream_t (as void*); all work is enqueued on it; the call
+ *     returns without waiting.
+ * Within a call, a node whose slice bits do not change between consecutive
+ * slices keeps its resident table instead of being contracted again; nothing
+ * is carried from one call to the next.
+ * Errors: XEB_EINVAL (range), XEB_ESTATE (no workspace), XEB_EHIP.
+ */
+int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* amps,
+                 void* stream);
+
+/*
+ * Linear XEB, Eq. (1): F = (2^n / k) sum_i |amps[i]|^2 - 1 over all k strings
+ * (duplicates with multiplicity), summed in FP64 with compensation on the
+ * device in a fixed order.  amps (device) complex128 [k].  Waits for the stream
+ * and writes *F (host).
+ * Errors: XEB_EINVAL (k == 0 or NULL F), XEB_ESTATE (no workspace), XEB_EHIP.
+ */
+int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F);
+
+/* Plan-wide figures (cost measures of Appendix A/C with exact variant counts). */
+int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats);
+
+/* Per-node figures; node = n_leaves + i for internal node i. */
+int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* stats);
+
+/* Release the plan's host memory (the workspace stays the caller's). */
+int xeb_plan_destroy(xeb_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XEB_H */

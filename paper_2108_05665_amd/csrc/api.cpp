@@ -1,0 +1,165 @@
+// C ABI entry points (xeb.h): argument checks, error capture, no exceptions
+// across the boundary.
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.h"
+#include "xeb.h"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    g_last_error = "no error";
+    return XEB_OK;
+  } catch (const xeb::Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return XEB_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return XEB_EINVAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return XEB_EINVAL;
+  }
+}
+
+xeb::Plan& impl(xeb_plan_t p) {
+  if (!p) xeb::fail(XEB_EINVAL, "plan handle is NULL");
+  return p->impl;
+}
+
+}  // namespace
+
+extern "C" {
+
+void xeb_options_default(xeb_options_t* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->fuse_1q = 1;
+  opt->fold_kets = 1;
+  opt->precision = XEB_PREC_C64;
+  opt->device = 0;
+  opt->memory_budget = 0;
+  opt->trace = 0;
+  opt->force_generic = 0;
+}
+
+const char* xeb_last_error(void) { return g_last_error.c_str(); }
+
+int xeb_network_describe(const xeb_circuit_t* circuit, int32_t fuse_1q, int32_t fold_kets,
+                         int32_t* n_leaves, int32_t* n_legs, int32_t* n_leaf_legs,
+                         int32_t* leaf_leg_offsets, int32_t* leaf_legs, int32_t* leg_qubit) {
+  return guarded([&] {
+    xeb::Net net = xeb::build_net(circuit, fuse_1q != 0, fold_kets != 0);
+    int32_t total = 0;
+    for (const auto& lf : net.leaves) total += int32_t(lf.legs.size());
+    if (n_leaves) *n_leaves = int32_t(net.leaves.size());
+    if (n_legs) *n_legs = net.n_legs;
+    if (n_leaf_legs) *n_leaf_legs = total;
+    if (leaf_leg_offsets) {
+      int32_t o = 0;
+      for (size_t j = 0; j < net.leaves.size(); ++j) {
+        leaf_leg_offsets[j] = o;
+        o += int32_t(net.leaves[j].legs.size());
+      }
+      leaf_leg_offsets[net.leaves.size()] = o;
+    }
+    if (leaf_legs) {
+      int32_t o = 0;
+      for (const auto& lf : net.leaves)
+        for (int32_t l : lf.legs) leaf_legs[o++] = l;
+    }
+    if (leg_qubit)
+      for (int l = 0; l < net.n_legs; ++l) leg_qubit[l] = net.leg_qubit[l];
+  });
+}
+
+int xeb_plan_create(const xeb_circuit_t* circuit, const uint64_t* bitstrings, int64_t k,
+                    const xeb_tree_t* contraction_tree, const int32_t* sliced_legs, int32_t s,
+                    const xeb_options_t* opt, xeb_plan_t* out) {
+  return guarded([&] {
+    if (!out) xeb::fail(XEB_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    xeb_plan* p = new xeb_plan();
+    try {
+      xeb::compile_plan(p->impl, circuit, bitstrings, k, contraction_tree, sliced_legs, s, opt);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+int xeb_plan_workspace_bytes(xeb_plan_t plan, uint64_t* bytes) {
+  return guarded([&] {
+    xeb::Plan& p = impl(plan);
+    if (!bytes) xeb::fail(XEB_EINVAL, "bytes is NULL");
+    *bytes = p.ws_bytes;
+  });
+}
+
+int xeb_plan_bind_workspace(xeb_plan_t plan, void* dev_ptr, uint64_t bytes) {
+  return guarded([&] { xeb::bind_plan(&impl(plan), dev_ptr, bytes); });
+}
+
+int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* amps,
+                 void* stream) {
+  return guarded([&] {
+    xeb::contract_plan(&impl(plan), slice_begin, slice_end, amps,
+                       static_cast<hipStream_t>(stream));
+  });
+}
+
+int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F) {
+  return guarded([&] {
+    if (!F) xeb::fail(XEB_EINVAL, "F is NULL");
+    *F = xeb::fidelity_plan(&impl(plan), amps, static_cast<hipStream_t>(stream));
+  });
+}
+
+int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats) {
+  return guarded([&] {
+    if (!stats) xeb::fail(XEB_EINVAL, "stats is NULL");
+    *stats = impl(plan).stats;
+  });
+}
+
+int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
+  return guarded([&] {
+    xeb::Plan& p = impl(plan);
+    if (!st) xeb::fail(XEB_EINVAL, "stats is NULL");
+    if (node < p.n_leaves || node >= int32_t(p.nodes.size()))
+      xeb::fail(XEB_EINVAL, "node is not an internal node id");
+    const xeb::Node& nd = p.nodes[node];
+    std::memset(st, 0, sizeof(*st));
+    st->left = nd.left;
+    st->right = nd.right;
+    st->variants = nd.nvar;
+    st->left_variants = p.nodes[nd.left].nvar;
+    st->right_variants = p.nodes[nd.right].nvar;
+    st->m_bits = nd.mb;
+    st->n_bits = nd.nb;
+    st->k_bits = nd.kb;
+    st->slice_mask = nd.smask;
+    st->kernel = nd.kernel;
+    st->swapped = 0;
+    st->cmacs_per_eval = double(nd.nvar) * double(uint64_t(1) << (nd.mb + nd.nb + nd.kb));
+  });
+}
+
+int xeb_plan_destroy(xeb_plan_t plan) {
+  return guarded([&] { delete plan; });
+}
+
+}  // extern "C"

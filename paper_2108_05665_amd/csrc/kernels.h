@@ -1,0 +1,46 @@
+// Launch interfaces of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace xeb {
+
+constexpr int kMaxBits = 48;  // max legs of one tensor (bits of its element index)
+
+// One pairwise contraction T = L * R over all variants of T (Appendix A:
+// 2^(q+r) complex MACs per variant).  Operand layouts: a variant of L is a
+// row-major (2^mb x 2^kb) matrix (shared legs in the low bits), a variant of
+// R a row-major (2^nb x 2^kb) matrix; element (m, n) of a variant of T lives
+// at offset dep(m, posM) + dep(n, posN), where dep deposits bit j of its
+// argument at bit position pos[j].
+struct ContractArgs {
+  const float2* A;       // L table (variants x 2^(mb+kb))
+  const float2* B;       // R table (variants x 2^(nb+kb))
+  float2* C;             // T table (variants x 2^(mb+nb))
+  const int32_t* lidx;   // generic kernel: L variant of each T variant
+  const int32_t* ridx;   // generic kernel: R variant of each T variant
+  const int32_t* pairs;  // MFMA kernel, table mode: T variant of (l, r) or -1
+  int64_t nvar;          // T variants
+  int64_t nvarA, nvarB;  // L and R variants
+  int32_t mb, nb, kb;
+  int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table
+  int8_t posM[kMaxBits];
+  int8_t posN[kMaxBits];
+};
+
+void launch_contract_generic(const ContractArgs& a, hipStream_t s);
+void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
+
+// Cross-slice accumulation (Appendix A, "Slicing": sum over assignments) in
+// FP64 with Neumaier compensation: amps[i] += partial[rho[i]].
+void launch_zero(void* p, uint64_t bytes, hipStream_t s);
+void launch_accumulate(const float2* partial, const int32_t* rho, double2* amps, double2* comp,
+                       int64_t k, hipStream_t s);
+void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s);
+
+// Linear XEB (Eq. 1): out[0] = 2^n / k * sum |amps|^2 - 1.
+void launch_xeb(const double2* amps, int64_t k, int n_qubits, double* out, hipStream_t s);
+
+}  // namespace xeb

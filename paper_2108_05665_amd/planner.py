@@ -1,0 +1,232 @@
+"""Contraction-tree and slicing planner (host side).
+
+Produces the `contraction_tree` and `sliced_legs` inputs of xeb_plan_create.
+
+* Tree: randomized greedy over connected pairs.  The score of contracting a
+  and b compares the size of the result with the sizes of the operands, each
+  weighted by its number of distinct string keys (the evaluation count k_T of
+  Appendix C), so the batch's shared sub-contractions are preferred; several
+  randomized trials keep the cheapest tree under the multi-tensor cost
+  C(T, k) = sum_T k_T 2^(q_T + r_T) (Appendix C, "Complexity estimation").
+* Slicing: the paper's rule of adding the leg that gives the best memory
+  reduction (Appendix A, "Slicing"), applied greedily until the requested
+  number of legs is sliced (ties: lower total cost).
+* Slice-bit order: slices run in increasing id order and a node is contracted
+  again only when one of its slice bits changes, so the legs that expensive
+  nodes depend on get the high bits (greedy from bit 0 upwards).
+
+The simulated-annealing optimizer of Appendix A is not part of this module.
+"""
+
+from __future__ import annotations
+
+import math
+import random
+
+import numpy as np
+
+from . import xeb as _xeb
+
+
+class Structure:
+    """Leaf legs (internal legs only) and output masks of a circuit's network."""
+
+    def __init__(self, circ, fuse_1q=True, fold_kets=True):
+        leaves, n_legs, leg_qubit = _xeb.network_describe(circ, fuse_1q, fold_kets)
+        self.n_legs = n_legs
+        self.leg_qubit = leg_qubit
+        self.legs = []
+        self.outmask = []
+        for legs in leaves:
+            om = 0
+            internal = []
+            for l in legs:
+                q = leg_qubit[l]
+                if q >= 0:
+                    om |= 1 << q
+                else:
+                    internal.append(l)
+            self.legs.append(frozenset(internal))
+            self.outmask.append(om)
+        self.n_leaves = len(leaves)
+
+
+class VariantCounter:
+    """Number of distinct keys s & mask over the distinct strings (cached)."""
+
+    def __init__(self, bitstrings):
+        self.s = np.unique(np.asarray(bitstrings, dtype=np.uint64))
+        self.cache = {0: 1}
+
+    def __call__(self, mask: int) -> int:
+        r = self.cache.get(mask)
+        if r is None:
+            r = int(np.unique(self.s & np.uint64(mask)).size) if self.s.size else 1
+            self.cache[mask] = max(r, 1)
+            r = self.cache[mask]
+        return r
+
+
+def greedy_tree(st: Structure, count: VariantCounter, rng: random.Random, temp: float):
+    act = {i: (st.legs[i], st.outmask[i]) for i in range(st.n_leaves)}
+    owners = {}
+    for i, (legs, _) in act.items():
+        for l in legs:
+            owners.setdefault(l, set()).add(i)
+    children = []
+    nid = st.n_leaves
+    while len(act) > 1:
+        cands = set()
+        for l, who in owners.items():
+            if len(who) == 2:
+                a, b = sorted(who)
+                cands.add((a, b))
+        if not cands:
+            ks = sorted(act)
+            cands = {(ks[0], ks[1])}
+        best = None
+        for a, b in sorted(cands):
+            la, oa = act[a]
+            lb, ob = act[b]
+            res = la ^ lb
+            out = math.log2(count(oa | ob)) + len(res)
+            inp = math.log2(count(oa) * 2.0 ** len(la) + count(ob) * 2.0 ** len(lb))
+            score = out - inp
+            if temp > 0:
+                score -= temp * -math.log(-math.log(rng.random() or 1e-300))
+            if best is None or score < best[0]:
+                best = (score, a, b)
+        _, a, b = best
+        la, oa = act.pop(a)
+        lb, ob = act.pop(b)
+        res = la ^ lb
+        for l in la | lb:
+            owners[l].discard(a)
+            owners[l].discard(b)
+            if l in res:
+                owners[l].add(nid)
+            else:
+                del owners[l]
+        act[nid] = (res, oa | ob)
+        children.append((a, b))
+        nid += 1
+    return children
+
+
+def node_sets(st: Structure, children, sliced=frozenset()):
+    """Per node: legs (after slicing), outmask, set of sliced legs below."""
+    legs = [l - sliced for l in st.legs]
+    full = list(st.legs)
+    om = list(st.outmask)
+    sdep = [l & sliced for l in st.legs]
+    for a, b in children:
+        full.append(full[a] ^ full[b])
+        legs.append(full[-1] - sliced)
+        om.append(om[a] | om[b])
+        sdep.append(sdep[a] | sdep[b])
+    return full, legs, om, sdep
+
+
+def tree_cost(st: Structure, children, count: VariantCounter, sliced=(), order=None):
+    """Multi-tensor cost over all slices under the executor's schedule, the
+    largest tensor (log2 elements) after slicing, and per-slice cost."""
+    sliced = frozenset(sliced)
+    bit = {l: j for j, l in enumerate(order)} if order is not None else None
+    full, legs, om, sdep = node_sets(st, children, sliced)
+    L = st.n_leaves
+    s = len(sliced)
+    total = 0.0
+    per_slice = 0.0
+    maxsz = max((len(x) for x in legs), default=0)
+    for i, (a, b) in enumerate(children):
+        t = L + i
+        allg = (full[a] | full[b]) - sliced
+        c = count(om[t]) * 2.0 ** len(allg)
+        per_slice += c
+        if not sdep[t]:
+            ev = 1.0
+        elif bit is None:
+            ev = 2.0 ** len(sdep[t])        # ideal reuse across slices
+        else:
+            ev = 2.0 ** (s - min(bit[l] for l in sdep[t]))
+        total += ev * c
+    return total, maxsz, per_slice
+
+
+def greedy_slices(st: Structure, children, count: VariantCounter, n_slice: int,
+                  max_candidates: int = 64):
+    """Add legs one at a time, each the one that most reduces the largest
+    tensor (ties: lower cost)."""
+    sliced = set()
+    for _ in range(n_slice):
+        full, legs, om, sdep = node_sets(st, children, frozenset(sliced))
+        maxsz = max(len(x) for x in legs)
+        cand = set()
+        for x in legs:
+            if len(x) >= maxsz - 1:
+                cand |= x
+        if not cand:
+            for x in legs:
+                cand |= x
+        cand = sorted(cand)[: max(max_candidates, 1) * 8]
+        best = None
+        for l in cand:
+            tot, mx, _ = tree_cost(st, children, count, sliced | {l})
+            key = (mx, tot, l)
+            if best is None or key < best[0]:
+                best = (key, l)
+        if best is None:
+            break
+        sliced.add(best[1])
+    return sorted(sliced)
+
+
+def order_slices(st: Structure, children, count: VariantCounter, sliced):
+    """Slice-id bit order: bit b goes to the leg whose dependent, not yet
+    assigned nodes cost least when recomputed every 2^b slices."""
+    sliced = list(sliced)
+    full, legs, om, sdep = node_sets(st, children, frozenset(sliced))
+    L = st.n_leaves
+    costs = []
+    for i, (a, b) in enumerate(children):
+        t = L + i
+        allg = (full[a] | full[b]) - frozenset(sliced)
+        costs.append((sdep[t], count(om[t]) * 2.0 ** len(allg)))
+    order = []
+    covered = [False] * len(costs)
+    remaining = set(sliced)
+    while remaining:
+        best = None
+        for l in sorted(remaining):
+            add = sum(c for j, (dep, c) in enumerate(costs) if not covered[j] and l in dep)
+            if best is None or add < best[0]:
+                best = (add, l)
+        l = best[1]
+        order.append(l)
+        remaining.discard(l)
+        for j, (dep, _) in enumerate(costs):
+            if l in dep:
+                covered[j] = True
+    return order
+
+
+def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
+         temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True):
+    """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info)."""
+    st = Structure(circ, fuse_1q, fold_kets)
+    count = VariantCounter(bitstrings)
+    if st.n_leaves == 1:
+        return [], [], dict(cost=0.0, max_log2=0)
+    rng = random.Random(seed)
+    best = None
+    for t in range(max(trials, 1)):
+        ch = greedy_tree(st, count, rng, 0.0 if t == 0 else temp)
+        c, mx, _ = tree_cost(st, ch, count)
+        if best is None or c < best[0]:
+            best = (c, ch)
+    ch = best[1]
+    sliced = greedy_slices(st, ch, count, n_sliced) if n_sliced else []
+    order = order_slices(st, ch, count, sliced) if sliced else []
+    total, mx, per_slice = tree_cost(st, ch, count, order, order)
+    info = dict(cost=total, cost_per_slice=per_slice, max_log2=mx, unsliced_cost=best[0])
+    return ch, order, info

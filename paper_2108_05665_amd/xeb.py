@@ -1,0 +1,285 @@
+"""ctypes binding of libxeb.so (the C ABI in include/xeb.h).
+
+Argument marshalling only: every step of the contraction runs in the
+library's gfx950 kernels.  PyTorch supplies device memory (the plan's
+workspace and the amplitude buffer) and streams.  If libxeb.so is missing
+this module raises at import: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxeb.so")
+
+XEB_OK = 0
+XEB_EINVAL = -1
+XEB_ENOMEM = -2
+XEB_EHIP = -3
+XEB_ESTATE = -4
+
+PRECISIONS = {"c64": 0, "split_fp16": 1, "split_bf16": 2}
+KERNELS = {0: "generic", 1: "mfma"}
+
+# torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it first
+# makes libxeb's libamdhip64.so.7 dependency resolve to that same copy; a second
+# runtime in the process would not see the GPU.
+import torch  # noqa: E402,F401
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "(hipcc --offload-arch=gfx950); there is no CPU fallback"
+    )
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class XebError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"xeb error {code}: {msg}")
+        self.code = code
+
+
+class Circuit(ctypes.Structure):
+    _fields_ = [
+        ("n_qubits", ctypes.c_int32),
+        ("n_gates", ctypes.c_int32),
+        ("gate_qubits", ctypes.POINTER(ctypes.c_int32)),
+        ("gate_mats", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class Tree(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int32), ("children", ctypes.POINTER(ctypes.c_int32))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("fuse_1q", ctypes.c_int32),
+        ("fold_kets", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("memory_budget", ctypes.c_uint64),
+        ("trace", ctypes.c_int32),
+        ("force_generic", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_leaves", ctypes.c_int64),
+        ("n_internal", ctypes.c_int64),
+        ("k", ctypes.c_int64),
+        ("k_distinct", ctypes.c_int64),
+        ("n_qubits", ctypes.c_int32),
+        ("n_sliced", ctypes.c_int32),
+        ("sum_variants", ctypes.c_int64),
+        ("max_tensor_elems", ctypes.c_int64),
+        ("cmacs_per_slice", ctypes.c_double),
+        ("cmacs_full", ctypes.c_double),
+        ("rw_elems_full", ctypes.c_double),
+        ("evals_full", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class NodeStats(ctypes.Structure):
+    _fields_ = [
+        ("left", ctypes.c_int32),
+        ("right", ctypes.c_int32),
+        ("variants", ctypes.c_int64),
+        ("left_variants", ctypes.c_int64),
+        ("right_variants", ctypes.c_int64),
+        ("m_bits", ctypes.c_int32),
+        ("n_bits", ctypes.c_int32),
+        ("k_bits", ctypes.c_int32),
+        ("slice_mask", ctypes.c_uint64),
+        ("kernel", ctypes.c_int32),
+        ("swapped", ctypes.c_int32),
+        ("cmacs_per_eval", ctypes.c_double),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_SIG = {
+    "xeb_options_default": (None, [ctypes.POINTER(Options)]),
+    "xeb_last_error": (ctypes.c_char_p, []),
+    "xeb_network_describe": (ctypes.c_int, [ctypes.POINTER(Circuit), ctypes.c_int32, ctypes.c_int32,
+                                            _I32P, _I32P, _I32P, _I32P, _I32P, _I32P]),
+    "xeb_plan_create": (ctypes.c_int, [ctypes.POINTER(Circuit), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.c_int64, ctypes.POINTER(Tree), _I32P, ctypes.c_int32,
+                                       ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "xeb_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    "xeb_plan_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "xeb_contract": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "xeb_fidelity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "xeb_plan_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "xeb_plan_node_stats": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeStats)]),
+    "xeb_plan_destroy": (ctypes.c_int, [_P]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIG)
+
+
+def _check(rc: int) -> None:
+    if rc != XEB_OK:
+        raise XebError(rc, _lib.xeb_last_error().decode())
+
+
+def _circuit_struct(circ):
+    gq = np.ascontiguousarray(circ.gate_qubits, dtype=np.int32).reshape(-1, 2)
+    gm = np.ascontiguousarray(circ.gate_mats_f64(), dtype=np.float64)
+    c = Circuit(int(circ.n_qubits), int(gq.shape[0]),
+                gq.ctypes.data_as(_I32P), gm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return c, (gq, gm)  # keep the arrays alive with the struct
+
+
+def default_options() -> Options:
+    o = Options()
+    _lib.xeb_options_default(ctypes.byref(o))
+    return o
+
+
+def network_describe(circ, fuse_1q: bool = True, fold_kets: bool = True):
+    """Leaves (list of leg-id lists), number of legs, leg -> output qubit (-1)."""
+    c, keep = _circuit_struct(circ)
+    nl, ng, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.xeb_network_describe(ctypes.byref(c), int(fuse_1q), int(fold_kets),
+                                     ctypes.byref(nl), ctypes.byref(ng), ctypes.byref(nt),
+                                     None, None, None))
+    offs = np.zeros(nl.value + 1, dtype=np.int32)
+    legs = np.zeros(max(nt.value, 1), dtype=np.int32)
+    lq = np.zeros(max(ng.value, 1), dtype=np.int32)
+    _check(_lib.xeb_network_describe(ctypes.byref(c), int(fuse_1q), int(fold_kets),
+                                     ctypes.byref(nl), ctypes.byref(ng), ctypes.byref(nt),
+                                     offs.ctypes.data_as(_I32P), legs.ctypes.data_as(_I32P),
+                                     lq.ctypes.data_as(_I32P)))
+    leaves = [legs[offs[j]:offs[j + 1]].tolist() for j in range(nl.value)]
+    return leaves, ng.value, lq[: ng.value].tolist()
+
+
+class Plan:
+    """A compiled multi-tensor contraction (xeb_plan_create) bound to a
+    torch-allocated device workspace."""
+
+    def __init__(self, circ, bitstrings, tree_children, sliced_legs=(), *, fuse_1q=True,
+                 fold_kets=True, precision="c64", device=None, memory_budget=0, trace=0,
+                 force_generic=False, bind=True):
+        self._h = _P()
+        c, keep = _circuit_struct(circ)
+        bs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
+        ch = np.ascontiguousarray(np.asarray(tree_children, dtype=np.int32).reshape(-1))
+        n_leaves = ch.size // 2 + 1
+        tree = Tree(n_leaves, ch.ctypes.data_as(_I32P) if ch.size else None)
+        sl = np.ascontiguousarray(np.asarray(list(sliced_legs), dtype=np.int32))
+        o = default_options()
+        o.fuse_1q = int(fuse_1q)
+        o.fold_kets = int(fold_kets)
+        o.precision = PRECISIONS[precision]
+        self._device_index = 0 if device is None else int(device)
+        o.device = self._device_index
+        o.memory_budget = int(memory_budget)
+        o.trace = int(trace)
+        o.force_generic = int(force_generic)
+        _check(_lib.xeb_plan_create(ctypes.byref(c), bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    bs.size, ctypes.byref(tree),
+                                    sl.ctypes.data_as(_I32P) if sl.size else None, sl.size,
+                                    ctypes.byref(o), ctypes.byref(self._h)))
+        self.k = int(bs.size)
+        self.n_qubits = int(circ.n_qubits)
+        self.n_slices = 1 << int(sl.size)
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    # -- device memory ------------------------------------------------------
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(_lib.xeb_plan_workspace_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def bind(self, workspace=None):
+        import torch
+
+        nbytes = self.workspace_bytes()
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                    device=torch.device("cuda", self._device_index))
+        ptr = workspace.data_ptr()
+        aligned = (ptr + 255) // 256 * 256
+        avail = workspace.numel() - (aligned - ptr)
+        _check(_lib.xeb_plan_bind_workspace(self._h, ctypes.c_void_p(aligned), avail))
+        self.workspace = workspace
+        return workspace
+
+    def new_amps(self):
+        import torch
+
+        return torch.zeros(self.k, dtype=torch.complex128,
+                           device=torch.device("cuda", self._device_index))
+
+    @staticmethod
+    def _stream_handle(stream):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    # -- the hot path ---------------------------------------------------------
+    def contract(self, amps, slice_begin: int = 0, slice_end: int | None = None, stream=None):
+        if slice_end is None:
+            slice_end = self.n_slices
+        import torch
+
+        if amps.dtype != torch.complex128 or not amps.is_cuda or amps.numel() < self.k:
+            raise ValueError("amps must be a CUDA complex128 tensor with k elements")
+        if not amps.is_contiguous():
+            raise ValueError("amps must be contiguous")
+        _check(_lib.xeb_contract(self._h, int(slice_begin), int(slice_end),
+                                 ctypes.c_void_p(amps.data_ptr()), self._stream_handle(stream)))
+        return amps
+
+    def fidelity(self, amps, stream=None) -> float:
+        f = ctypes.c_double()
+        _check(_lib.xeb_fidelity(self._h, ctypes.c_void_p(amps.data_ptr()),
+                                 self._stream_handle(stream), ctypes.byref(f)))
+        return float(f.value)
+
+    # -- introspection ---------------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.xeb_plan_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def node_stats(self, node: int) -> dict:
+        s = NodeStats()
+        _check(_lib.xeb_plan_node_stats(self._h, int(node), ctypes.byref(s)))
+        d = {name: getattr(s, name) for name, _ in NodeStats._fields_}
+        d["kernel"] = KERNELS.get(d["kernel"], d["kernel"])
+        return d
+
+    def all_node_stats(self) -> list:
+        st = self.stats()
+        L = int(st["n_leaves"])
+        return [dict(node=L + i, **self.node_stats(L + i)) for i in range(int(st["n_internal"]))]
+
+    def close(self):
+        if self._h:
+            _lib.xeb_plan_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

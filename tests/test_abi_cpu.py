@@ -1,0 +1,153 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every
+declared symbol, the network convention agrees with the oracle's independent
+implementation, plan compilation yields the oracle's exact evaluation counts,
+and malformed inputs are rejected with XEB_EINVAL."""
+
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import grid_circuit, worked_example_circuit, uniform_bitstrings, prefix_bitstrings
+from oracle.network import build_network
+from oracle import memo
+from paper_2108_05665_amd import xeb, planner
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "xeb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xeb_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    import ctypes
+
+    lib = ctypes.CDLL(xeb.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(xeb.EXPORTED)
+
+
+@pytest.mark.parametrize("fuse,fold", [(1, 1), (0, 0), (1, 0), (0, 1)])
+@pytest.mark.parametrize("shape", [(3, 4, 6, 5), (2, 2, 1, 9), (1, 3, 2, 4), (4, 5, 8, 1001)])
+def test_network_convention_matches_oracle(fuse, fold, shape):
+    c = grid_circuit(*shape)
+    leaves, n_legs, leg_qubit = xeb.network_describe(c, fuse, fold)
+    net = build_network(c, bool(fuse), bool(fold))
+    assert leaves == net.leaf_legs()
+    assert n_legs == net.n_legs
+    assert leg_qubit == net.leg_qubit
+
+
+def test_network_untouched_qubit_gets_a_ket():
+    from synth.circuits import _Builder, SQRT_X
+
+    b = _Builder(3)
+    b.g1(0, SQRT_X)
+    c = b.build({})
+    for fuse, fold in [(1, 1), (0, 1), (1, 0), (0, 0)]:
+        leaves, n_legs, lq = xeb.network_describe(c, fuse, fold)
+        net = build_network(c, bool(fuse), bool(fold))
+        assert leaves == net.leaf_legs()
+        assert lq == net.leg_qubit
+
+
+def _counts_match(c, strings, trials=3, n_sliced=0):
+    ch, sl, info = planner.plan(c, strings, n_sliced=n_sliced, trials=trials)
+    p = xeb.Plan(c, strings, ch, sl, bind=False)
+    net = build_network(c)
+    tree = memo.Tree(len(net.leaves), ch)
+    want = memo.distinct_key_counts(net, tree, strings)
+    got = {ns["node"]: ns["variants"] for ns in p.all_node_stats()}
+    assert got == want
+    st = p.stats()
+    assert st["sum_variants"] == sum(want.values())
+    assert st["k_distinct"] == len(set(int(x) for x in strings))
+    assert abs(st["cmacs_full"] - info["cost"]) <= 1e-9 * max(1.0, info["cost"])
+    return p
+
+
+def test_worked_example_counts_through_abi():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "worked_example.json")))
+    strings = [sum(int(ch) << q for q, ch in enumerate(s)) for s in g["strings_q0_first"]]
+    p = xeb.Plan(worked_example_circuit(), strings, g["tree_children"], fuse_1q=False,
+                 fold_kets=False, bind=False)
+    got = {ns["node"]: ns["variants"] for ns in p.all_node_stats()}
+    assert got == {int(k): v for k, v in g["node_counts"].items()}
+    assert p.stats()["sum_variants"] == g["total_contractions_memo"]
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 300])
+def test_plan_counts_match_oracle(k):
+    c = grid_circuit(3, 4, 5, 40 + k)
+    _counts_match(c, uniform_bitstrings(12, k, k))
+
+
+def test_plan_counts_duplicates_and_prefix():
+    c = grid_circuit(3, 4, 6, 77)
+    s = prefix_bitstrings(12, 200, 7, 78)
+    s = np.concatenate([s, s[:50]])  # duplicates
+    _counts_match(c, s, n_sliced=2)
+
+
+def test_plan_counts_all_strings():
+    c = grid_circuit(2, 3, 4, 79)
+    allstr = np.arange(64, dtype=np.uint64)
+    p = _counts_match(c, allstr)
+    net = build_network(c)
+    for ns in p.all_node_stats():
+        tree_leaves = memo.Tree(len(net.leaves), [(x["left"], x["right"]) for x in p.all_node_stats()])
+        nout = sum(1 for j in tree_leaves.leaves_dfs(ns["node"]) for l in net.leaves[j].legs
+                   if net.leg_qubit[l] >= 0)
+        assert ns["variants"] == 2 ** nout
+
+
+def test_plan_rejects_bad_inputs():
+    c = grid_circuit(2, 3, 4, 80)
+    s = uniform_bitstrings(6, 10, 81)
+    ch, sl, _ = planner.plan(c, s, n_sliced=1, trials=1)
+    with pytest.raises(xeb.XebError) as e:  # a child used twice
+        bad = [list(x) for x in ch]
+        bad[-1][0] = bad[-2][0] if bad[-2][0] != bad[-1][1] else bad[-2][1]
+        xeb.Plan(c, s, bad, sl, bind=False)
+    assert e.value.code == xeb.XEB_EINVAL
+    with pytest.raises(xeb.XebError):  # too few internal nodes
+        xeb.Plan(c, s, ch[:-1], sl, bind=False)
+    net = build_network(c)
+    with pytest.raises(xeb.XebError):  # slicing an output leg
+        xeb.Plan(c, s, ch, [net.out_leg[0]], bind=False)
+    with pytest.raises(xeb.XebError):  # duplicate slice
+        xeb.Plan(c, s, ch, [sl[0], sl[0]], bind=False)
+    with pytest.raises(xeb.XebError):  # bit above n
+        xeb.Plan(c, np.array([1 << 6], dtype=np.uint64), ch, sl, bind=False)
+    with pytest.raises(xeb.XebError):  # memory budget
+        xeb.Plan(c, s, ch, sl, memory_budget=16, bind=False)
+
+
+def test_plan_empty_batch_compiles():
+    c = grid_circuit(2, 2, 3, 82)
+    ch, sl, _ = planner.plan(c, uniform_bitstrings(4, 3, 1), trials=1)
+    p = xeb.Plan(c, np.zeros(0, dtype=np.uint64), ch, sl, bind=False)
+    assert p.stats()["k"] == 0
+
+
+def test_planner_tree_is_valid_and_slices_reduce_size():
+    c = grid_circuit(4, 5, 8, 1001)
+    s = uniform_bitstrings(20, 300, 2001)
+    ch0, _, info0 = planner.plan(c, s, n_sliced=0, trials=4)
+    ch, sl, info = planner.plan(c, s, n_sliced=4, trials=4)
+    assert len(sl) == 4 and len(set(sl)) == 4
+    assert info["max_log2"] <= info0["max_log2"]
+    L = len(ch) + 1
+    seen = set()
+    for i, (a, b) in enumerate(ch):
+        assert a < L + i and b < L + i and a not in seen and b not in seen
+        seen |= {a, b}
+    assert len(seen) == 2 * L - 2
