@@ -9,17 +9,19 @@ Definitions followed:
   of all assignments (Appendix A, paragraph "Slicing").  A sliced partial for
   assignment sigma fixes leg sliced[j] to bit j of sigma.
 
-The contraction order is the oracle's own: repeatedly contract the pair of
-tensors sharing a leg whose result is smallest (ties: the pair with the
-smallest tensor indices), then multiply the scalars of disconnected pieces.
-The result does not depend on that order (section "Tensor network
-contraction"), so any order checks any other.  Each pairwise step is one
-numpy.tensordot in complex128.
+The result does not depend on the order of the pairwise contractions
+(section "Tensor network contraction"), so the oracle picks its own order:
+a greedy over pairs of tensors sharing a leg, scored by
+2^|result| - 2^|a| - 2^|b|.  For large networks it repeats the greedy with
+random perturbations of the score and keeps the order with the fewest
+multiply-adds among those whose largest tensor stays under a cap.  Each
+pairwise step is one numpy.tensordot in complex128.
 """
 
 from __future__ import annotations
 
 import math
+import random
 
 import numpy as np
 
@@ -29,7 +31,7 @@ from .network import Network
 def _fix(tensor: np.ndarray, legs: list, fixed: dict):
     idx = []
     keep = []
-    for ax, leg in enumerate(legs):
+    for leg in legs:
         if leg in fixed:
             idx.append(int(fixed[leg]))
         else:
@@ -47,75 +49,137 @@ def fixed_legs(net: Network, bitstring: int, sliced=(), sigma: int = 0) -> dict:
     return fixed
 
 
-def contract_closed(tensors: list, order_rng=None) -> complex:
-    """Contract a list of (array, legs) whose legs each appear exactly twice
-    (closed network).  With `order_rng` the next pair is drawn at random among
-    the connected pairs instead of the greedy choice (order-independence pin).
-    """
-    items = [(np.asarray(t), list(l)) for t, l in tensors]
-    scalar = complex(1.0)
-    while True:
-        # Absorb scalars immediately.
-        rest = []
-        for t, l in items:
-            if not l:
-                scalar *= complex(t)
-            else:
-                rest.append((t, l))
-        items = rest
-        if not items:
-            return scalar
+def greedy_order(leg_sets, rng=None, noise: float = 0.0):
+    """Order of pairwise contractions for a closed network given the leg sets
+    of its tensors.  Returns (pairs, largest log2 size, multiply-adds) where
+    pairs index an SSA list: tensors 0..n-1, then result n+i of step i."""
+    items = {i: frozenset(s) for i, s in enumerate(leg_sets)}
+    nxt = len(items)
+    pairs = []
+    biggest = 0
+    madds = 0
+    while len(items) > 1:
         owner = {}
-        for i, (_, l) in enumerate(items):
-            for leg in l:
+        for i, s in items.items():
+            for leg in s:
                 owner.setdefault(leg, []).append(i)
-        pairs = set()
-        for leg, who in owner.items():
-            if len(who) == 2 and who[0] != who[1]:
-                pairs.add((min(who), max(who)))
-            elif len(who) != 2:
-                raise ValueError(f"leg {leg} is not closed")
-        if not pairs:
-            # A tensor with a leg appearing twice on itself would be a trace;
-            # the circuit networks never produce one.
-            raise ValueError("no contractible pair")
-        if order_rng is not None:
-            cand = sorted(pairs)
-            i, j = cand[int(order_rng.integers(0, len(cand)))]
-        else:
-            best = None
-            for i, j in sorted(pairs):
-                li, lj = set(items[i][1]), set(items[j][1])
-                size = len(li ^ lj)
-                if best is None or size < best[0]:
-                    best = (size, i, j)
-            _, i, j = best
-        (ti, li), (tj, lj) = items[i], items[j]
+        cand = sorted({(min(w), max(w)) for w in owner.values() if len(w) == 2})
+        if not cand:
+            keys = sorted(items)
+            cand = [(keys[0], keys[1])]  # disconnected pieces: outer product
+        best = None
+        for i, j in cand:
+            a, b = items[i], items[j]
+            r = a ^ b
+            sc = 2.0 ** len(r) - 2.0 ** len(a) - 2.0 ** len(b)
+            if noise > 0 and rng is not None:
+                sc = (len(r) - math.log2(2.0 ** len(a) + 2.0 ** len(b))
+                      + noise * math.log(-math.log(rng.random() or 1e-300)))
+            if best is None or sc < best[0]:
+                best = (sc, i, j, r)
+        _, i, j, r = best
+        madds += 2 ** len(items[i] | items[j])
+        biggest = max(biggest, len(r))
+        del items[i], items[j]
+        items[nxt] = r
+        pairs.append((i, j))
+        nxt += 1
+    return pairs, biggest, madds
+
+
+def search_order(leg_sets, trials: int = 64, seed: int = 1, cap_log2: int = 27):
+    """Best of one plain greedy and `trials` perturbed greedies: fewest
+    multiply-adds with the largest tensor <= 2^cap_log2 (else the smallest
+    largest tensor)."""
+    best = greedy_order(leg_sets)
+    rng = random.Random(seed)
+
+    def better(x, y):
+        fx, fy = x[1] <= cap_log2, y[1] <= cap_log2
+        if fx != fy:
+            return fx
+        return x[2] < y[2] if fx else (x[1], x[2]) < (y[1], y[2])
+
+    for _ in range(trials):
+        cand = greedy_order(leg_sets, rng, noise=0.5)
+        if better(cand, best):
+            best = cand
+    return best
+
+
+def _random_order(leg_sets, rng):
+    items = {i: frozenset(s) for i, s in enumerate(leg_sets)}
+    nxt = len(items)
+    pairs = []
+    while len(items) > 1:
+        owner = {}
+        for i, s in items.items():
+            for leg in s:
+                owner.setdefault(leg, []).append(i)
+        cand = sorted({(min(w), max(w)) for w in owner.values() if len(w) == 2})
+        if not cand:
+            keys = sorted(items)
+            cand = [(keys[0], keys[1])]
+        i, j = cand[int(rng.integers(0, len(cand)))]
+        r = items.pop(i) ^ items.pop(j)
+        items[nxt] = r
+        pairs.append((i, j))
+        nxt += 1
+    return pairs
+
+
+def contract_closed(tensors: list, pairs=None, order_rng=None) -> complex:
+    """Contract a closed network given as (array, legs) pairs.  `pairs` is an
+    SSA order (greedy_order); with `order_rng` a uniformly random connected
+    order is used instead (order-independence pin)."""
+    items = [(np.asarray(t), list(l)) for t, l in tensors]
+    for t, l in items:
+        if len(set(l)) != len(l):
+            raise ValueError("a tensor repeats a leg")
+    if pairs is None:
+        sets = [set(l) for _, l in items]
+        pairs = _random_order(sets, order_rng) if order_rng is not None else greedy_order(sets)[0]
+    store = dict(enumerate(items))
+    nxt = len(items)
+    for i, j in pairs:
+        (ti, li), (tj, lj) = store.pop(i), store.pop(j)
         shared = [leg for leg in li if leg in lj]
-        ai = [li.index(leg) for leg in shared]
-        aj = [lj.index(leg) for leg in shared]
-        t = np.tensordot(ti, tj, axes=(ai, aj))
-        legs = [leg for leg in li if leg not in shared] + [leg for leg in lj if leg not in shared]
-        items = [it for k, it in enumerate(items) if k not in (i, j)] + [(t, legs)]
+        t = np.tensordot(ti, tj, axes=([li.index(x) for x in shared], [lj.index(x) for x in shared]))
+        legs = [x for x in li if x not in shared] + [x for x in lj if x not in shared]
+        store[nxt] = (t, legs)
+        nxt += 1
+    (t, legs), = store.values()
+    if legs:
+        raise ValueError("network is not closed")
+    return complex(t)
+
+
+def leaf_tensors(net: Network, bitstring: int, sliced=(), sigma: int = 0):
+    fixed = fixed_legs(net, bitstring, sliced, sigma)
+    return [_fix(lf.tensor, lf.legs, fixed) for lf in net.leaves]
+
+
+def closed_leg_sets(net: Network, sliced=()):
+    sl = set(int(x) for x in sliced)
+    return [set(l for l in lf.legs if net.leg_qubit[l] < 0 and l not in sl) for lf in net.leaves]
 
 
 def partial_amplitude(net: Network, bitstring: int, sliced=(), sigma: int = 0,
-                      order_rng=None) -> complex:
+                      order_rng=None, pairs=None) -> complex:
     """Contraction of the network with the output legs fixed to `bitstring`
     and leg sliced[j] fixed to bit j of `sigma`."""
-    fixed = fixed_legs(net, bitstring, sliced, sigma)
-    tensors = [_fix(lf.tensor, lf.legs, fixed) for lf in net.leaves]
-    return contract_closed(tensors, order_rng)
+    return contract_closed(leaf_tensors(net, bitstring, sliced, sigma), pairs, order_rng)
 
 
-def amplitude(net: Network, bitstring: int, sliced=(), order_rng=None) -> complex:
+def amplitude(net: Network, bitstring: int, sliced=(), order_rng=None, pairs=None) -> complex:
     """amp(s) = sum over all 2^|sliced| assignments of the sliced partials,
     each part summed exactly (math.fsum)."""
-    parts = [partial_amplitude(net, bitstring, sliced, sigma, order_rng)
+    parts = [partial_amplitude(net, bitstring, sliced, sigma, order_rng, pairs)
              for sigma in range(1 << len(sliced))]
     return complex(math.fsum(p.real for p in parts), math.fsum(p.imag for p in parts))
 
 
 def amplitudes(net: Network, bitstrings, sliced=()) -> np.ndarray:
-    return np.array([amplitude(net, int(s), sliced) for s in bitstrings],
+    pairs = greedy_order(closed_leg_sets(net, sliced))[0]
+    return np.array([amplitude(net, int(s), sliced, pairs=pairs) for s in bitstrings],
                     dtype=np.complex128)
