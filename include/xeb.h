@@ -235,6 +235,27 @@ int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats);
 /* Per-node figures; node = n_leaves + i for internal node i. */
 int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* stats);
 
+/*
+ * Kernel timing with HIP events, for measurement.
+ * xeb_plan_set_profiling(plan, 1) clears earlier records and makes every later
+ * xeb_contract record a HIP event pair on its stream around each contraction
+ * launch (and around each slice accumulation); 0 stops recording.
+ * xeb_plan_read_profile waits for the recorded events and sums, over the
+ * launches of one kernel class (XEB_KERNEL_GENERIC, XEB_KERNEL_MFMA, or
+ * XEB_KERNEL_ACCUMULATE), the event-measured seconds and the algorithmic
+ * work: complex MACs sum |t_T| 2^(q+r) and bytes 8 (|L| + |R| + |T|) of the
+ * tables each launch reads and writes (Appendix A, measures C and RW).
+ */
+#define XEB_KERNEL_ACCUMULATE 2
+typedef struct {
+  int64_t launches;
+  double seconds;
+  double cmacs;
+  double bytes;
+} xeb_kernel_profile_t;
+int xeb_plan_set_profiling(xeb_plan_t plan, int32_t enable);
+int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t* out);
+
 /* Release the plan's host memory (the workspace stays the caller's). */
 int xeb_plan_destroy(xeb_plan_t plan);
 

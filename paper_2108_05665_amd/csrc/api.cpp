@@ -153,8 +153,20 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->k_bits = nd.kb;
     st->slice_mask = nd.smask;
     st->kernel = nd.kernel;
-    st->swapped = 0;
+    st->swapped = nd.kernel == XEB_KERNEL_MFMA ? nd.swapped : 0;
     st->cmacs_per_eval = double(nd.nvar) * double(uint64_t(1) << (nd.mb + nd.nb + nd.kb));
+  });
+}
+
+int xeb_plan_set_profiling(xeb_plan_t plan, int32_t enable) {
+  return guarded([&] { xeb::set_profiling(&impl(plan), enable != 0); });
+}
+
+int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t* out) {
+  return guarded([&] {
+    if (!out) xeb::fail(XEB_EINVAL, "out is NULL");
+    if (kernel < 0 || kernel > XEB_KERNEL_ACCUMULATE) xeb::fail(XEB_EINVAL, "unknown kernel class");
+    *out = xeb::read_profile(&impl(plan), kernel);
   });
 }
 

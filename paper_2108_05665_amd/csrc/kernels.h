@@ -26,12 +26,18 @@ struct ContractArgs {
   int64_t nvarA, nvarB;  // L and R variants
   int32_t mb, nb, kb;
   int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table
+  int32_t swapped;       // MFMA: rows are R's variants (A <- R, B <- L)
+  int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128
   int8_t posM[kMaxBits];
   int8_t posN[kMaxBits];
+  // MFMA epilogue write order: bit b of an element's number inside the tile is
+  // row bit ubit[b] (< 32) or column bit ubit[b] - 32.
+  int8_t ubit[16];
 };
 
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
+void mfma_tile_shape(int tile, int* bm, int* bn);
 
 // Cross-slice accumulation (Appendix A, "Slicing": sum over assignments) in
 // FP64 with Neumaier compensation: amps[i] += partial[rho[i]].

@@ -57,95 +57,176 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// MFMA contraction: workgroup tile 64 x 64 complex, 4 waves (2 x 2), each
-// wave one 32 x 32 block; K staged through LDS 16 complex at a time as
-// separate re / im planes, [k][plane][row] (+1 float padding per plane row).
-constexpr int BM = 64, BN = 64, TK = 16, PAD = 1;
+// MFMA contraction.  Workgroup tile BM x BN complex (64 x 64 or 32 x 128), four
+// waves, each one 32 x 32 block of v_mfma_f32_32x32x2f32.  K is staged through
+// LDS TK = 16 complex at a time as separate re / im planes [k][plane][row]
+// (+1 float padding); the next K tile is fetched into registers (16-byte loads,
+// consecutive lanes along one contiguous row) while the current one is
+// multiplied.  The epilogue parks the tile in LDS and writes it out in the
+// order of the output layout's bit positions (ubit), so a wave stores runs of
+// consecutive addresses.
+constexpr int TK = 16, PAD = 1;
 
+template <int BM, int BN>
+struct Tile {
+  static constexpr int WM = BM / 32;
+  static constexpr int WN = 4 / WM;
+  static_assert(WN * 32 == BN, "four 32x32 wave blocks per tile");
+  static constexpr int A_VEC = BM * TK / 2 / 256;
+  static constexpr int B_VEC = BN * TK / 2 / 256;
+  static constexpr int LDS_A = TK * 2 * (BM + PAD);
+  static constexpr int LDS_MAIN = LDS_A + TK * 2 * (BN + PAD);
+  static constexpr int LDS_EPI = BM * (BN + 1) * 2;
+  static constexpr int LDS = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
+  static constexpr int UBITS = (BM == 64 ? 6 : 5) + (BN == 64 ? 6 : 7);
+  static constexpr int PER_THREAD = BM * BN / 256;
+};
+
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
-  __shared__ float As[TK][2][BM + PAD];
-  __shared__ float Bs[TK][2][BN + PAD];
+  using T = Tile<BM, BN>;
+  __shared__ float smem[T::LDS];
+  __shared__ int64_t dep_m_lo[BM];
+  __shared__ int64_t dep_n_lo[BN];
+  float(*As)[2][BM + PAD] = reinterpret_cast<float(*)[2][BM + PAD]>(smem);
+  float(*Bs)[2][BN + PAD] = reinterpret_cast<float(*)[2][BN + PAD]>(smem + T::LDS_A);
+  float2* Ct = reinterpret_cast<float2*>(smem);
+
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / T::WN, wn = wave % T::WN;
   const int64_t rowsA = g.nvarA << g.mb;
   const int64_t rowsB = g.nvarB << g.nb;
   const int64_t tiles_n = (rowsB + BN - 1) / BN;
   const int64_t tiles = tiles_n * ((rowsA + BM - 1) / BM);
   const int64_t K = int64_t(1) << g.kb;
+  const int64_t M = int64_t(1) << g.mb;
+  const int64_t N = int64_t(1) << g.nb;
+  const int64_t sizeC = M * N;
+  const int64_t m_lo_mask = (M < BM ? M : BM) - 1;
+  const int64_t n_lo_mask = (N < BN ? N : BN) - 1;
+
+  for (int i = tid; i < BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.posM, g.mb);
+  for (int i = tid; i < BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.posN, g.nb);
+  // Row / column inside the tile of this thread's epilogue elements: bits 0..7
+  // of the element number come from tid, the rest from the loop counter.
+  int r_tid = 0, c_tid = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if ((tid >> b) & 1) {
+      const int u = g.ubit[b];
+      if (u < 32)
+        r_tid |= 1 << u;
+      else
+        c_tid |= 1 << (u - 32);
+    }
+  }
+  __syncthreads();
+
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-  const int64_t row0 = (tile / tiles_n) * BM;
-  const int64_t col0 = (tile % tiles_n) * BN;
+    const int64_t row0 = (tile / tiles_n) * BM;
+    const int64_t col0 = (tile % tiles_n) * BN;
 
-  floatx16 acc_re, acc_im;
-  for (int v = 0; v < 16; ++v) {
-    acc_re[v] = 0.f;
-    acc_im[v] = 0.f;
-  }
-
-  for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    // Stage: BM x TK complex of each operand, 4 elements per thread.  A
-    // thread's consecutive lanes walk k inside one row (contiguous in HBM).
-#pragma unroll
-    for (int t = 0; t < (BM * TK) / 256; ++t) {
-      const int e = tid + t * 256;
-      const int r = e / TK, kk = e % TK;
-      const int64_t gr = row0 + r, gk = k0 + kk;
-      float2 x = make_float2(0.f, 0.f);
-      if (gr < rowsA && gk < K) x = g.A[(gr << g.kb) + gk];
-      As[kk][0][r] = x.x;
-      As[kk][1][r] = x.y;
-    }
-#pragma unroll
-    for (int t = 0; t < (BN * TK) / 256; ++t) {
-      const int e = tid + t * 256;
-      const int r = e / TK, kk = e % TK;
-      const int64_t gr = col0 + r, gk = k0 + kk;
-      float2 x = make_float2(0.f, 0.f);
-      if (gr < rowsB && gk < K) x = g.B[(gr << g.kb) + gk];
-      Bs[kk][0][r] = x.x;
-      Bs[kk][1][r] = x.y;
-    }
-    __syncthreads();
-    const int i = lane & 31;
-    const int half = lane >> 5;  // 0: real plane of the K=2 pair, 1: imaginary
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      const float a = As[kk][half][wm * 32 + i];
-      const float bre = Bs[kk][0][wn * 32 + i];
-      const float bim = Bs[kk][1][wn * 32 + i];
-      const float b_for_re = half ? -bim : bre;
-      const float b_for_im = half ? bre : bim;
-      acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_re, acc_re, 0, 0, 0);
-      acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_im, acc_im, 0, 0, 0);
-    }
-    __syncthreads();
-  }
-
-  // Epilogue.  Output layout of v_mfma_f32_32x32x2f32: lane l, register v hold
-  // row (v % 4) + 4 (l / 32) + 8 (v / 4), column l % 32.
-  const int64_t mmask = (int64_t(1) << g.mb) - 1;
-  const int64_t nmask = (int64_t(1) << g.nb) - 1;
-  const int64_t sizeC = int64_t(1) << (g.mb + g.nb);
-  const int64_t gc = col0 + wn * 32 + (lane & 31);
-  if (gc < rowsB) {
-    const int64_t r_var = gc >> g.nb;
-    const int64_t n = gc & nmask;
-    const int64_t offn = deposit(n, g.posN, g.nb);
+    floatx16 acc_re, acc_im;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int64_t gr = row0 + wm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
-      if (gr >= rowsA) continue;
-      const int64_t l_var = gr >> g.mb;
-      const int64_t m = gr & mmask;
-      int64_t a = l_var * g.nvarB + r_var;
+      acc_re[v] = 0.f;
+      acc_im[v] = 0.f;
+    }
+
+    float4 ra[T::A_VEC], rb[T::B_VEC];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int t = 0; t < T::A_VEC; ++t) {
+        const int e = tid + t * 256;
+        const int r = e / (TK / 2), kp = e % (TK / 2);
+        const int64_t gr = row0 + r, gk = k0 + 2 * kp;
+        ra[t] = (gr < rowsA && gk < K)
+                    ? *reinterpret_cast<const float4*>(g.A + (gr << g.kb) + gk)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int t = 0; t < T::B_VEC; ++t) {
+        const int e = tid + t * 256;
+        const int r = e / (TK / 2), kp = e % (TK / 2);
+        const int64_t gr = col0 + r, gk = k0 + 2 * kp;
+        rb[t] = (gr < rowsB && gk < K)
+                    ? *reinterpret_cast<const float4*>(g.B + (gr << g.kb) + gk)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    fetch(0);
+    for (int64_t k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+      for (int t = 0; t < T::A_VEC; ++t) {
+        const int e = tid + t * 256;
+        const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
+        As[kk][0][r] = ra[t].x;
+        As[kk][1][r] = ra[t].y;
+        As[kk + 1][0][r] = ra[t].z;
+        As[kk + 1][1][r] = ra[t].w;
+      }
+#pragma unroll
+      for (int t = 0; t < T::B_VEC; ++t) {
+        const int e = tid + t * 256;
+        const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
+        Bs[kk][0][r] = rb[t].x;
+        Bs[kk][1][r] = rb[t].y;
+        Bs[kk + 1][0][r] = rb[t].z;
+        Bs[kk + 1][1][r] = rb[t].w;
+      }
+      __syncthreads();
+      if (k0 + TK < K) fetch(k0 + TK);
+      const int i = lane & 31;
+      const int half = lane >> 5;  // 0: real part of the K = 2 pair, 1: imaginary
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        const float a = As[kk][half][wm * 32 + i];
+        const float bre = Bs[kk][0][wn * 32 + i];
+        const float bim = Bs[kk][1][wn * 32 + i];
+        const float b_for_re = half ? -bim : bre;
+        const float b_for_im = half ? bre : bim;
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_re, acc_re, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_im, acc_im, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+
+    // Park the tile: lane l, register v of the MFMA result hold row
+    // (v % 4) + 4 (l / 32) + 8 (v / 4), column l % 32 of the wave's block.
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = wm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+      const int c = wn * 32 + (lane & 31);
+      Ct[r * (BN + 1) + c] = make_float2(acc_re[v], acc_im[v]);
+    }
+    __syncthreads();
+    const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.posM, g.mb) : 0;
+    const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.posN, g.nb) : 0;
+#pragma unroll 4
+    for (int t = 0; t < T::PER_THREAD; ++t) {
+      int r = r_tid, c = c_tid;
+#pragma unroll
+      for (int b = 8; b < T::UBITS; ++b) {
+        if ((t >> (b - 8)) & 1) {
+          const int u = g.ubit[b];
+          if (u < 32)
+            r |= 1 << u;
+          else
+            c |= 1 << (u - 32);
+        }
+      }
+      const int64_t gr = row0 + r, gc = col0 + c;
+      if (gr >= rowsA || gc >= rowsB) continue;
+      const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
+      int64_t a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
       if (g.pair_mode == 1) a = g.pairs[a];
       if (a < 0) continue;
-      g.C[a * sizeC + deposit(m, g.posM, g.mb) + offn] = make_float2(acc_re[v], acc_im[v]);
+      g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = Ct[r * (BN + 1) + c];
     }
+    __syncthreads();
   }
-  }  // tile loop
 }
 
 // ---------------------------------------------------------------------------
@@ -243,9 +324,18 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   const int64_t rowsA = a.nvarA << a.mb;
   const int64_t rowsB = a.nvarB << a.nb;
   if (rowsA <= 0 || rowsB <= 0) return;
-  const int64_t tiles = ((rowsB + BN - 1) / BN) * ((rowsA + BM - 1) / BM);
-  const int64_t grid = tiles < (int64_t(1) << 22) ? tiles : (int64_t(1) << 22);
-  k_contract_mfma<<<unsigned(grid), 256, 0, s>>>(a);
+  const int bm = a.tile == 0 ? 64 : 32, bn = a.tile == 0 ? 64 : 128;
+  const int64_t tiles = ((rowsB + bn - 1) / bn) * ((rowsA + bm - 1) / bm);
+  const unsigned grid = unsigned(tiles < (int64_t(1) << 22) ? tiles : (int64_t(1) << 22));
+  if (a.tile == 0)
+    k_contract_mfma<64, 64><<<grid, 256, 0, s>>>(a);
+  else
+    k_contract_mfma<32, 128><<<grid, 256, 0, s>>>(a);
+}
+
+void mfma_tile_shape(int tile, int* bm, int* bn) {
+  *bm = tile == 0 ? 64 : 32;
+  *bn = tile == 0 ? 64 : 128;
 }
 
 void launch_zero(void* p, uint64_t bytes, hipStream_t s) {

@@ -233,20 +233,39 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   }
 
   // ---- kernel per node ------------------------------------------------------
+  // MFMA when the stacked GEMM is big enough and its padded tile work stays
+  // within 8x the useful MACs; the smaller side supplies the tile rows.
   for (int T = L; T < nn; ++T) {
     Node& nd = p.nodes[T];
     const Node& a = p.nodes[nd.left];
     const Node& b = p.nodes[nd.right];
     const double useful = double(nd.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
-    const double rowsA = double(a.nvar) * std::ldexp(1.0, nd.mb);
-    const double rowsB = double(b.nvar) * std::ldexp(1.0, nd.nb);
+    const double rowsL = double(a.nvar) * std::ldexp(1.0, nd.mb);
+    const double rowsR = double(b.nvar) * std::ldexp(1.0, nd.nb);
     const double pairs = double(a.nvar) * double(b.nvar);
-    const double work = std::ceil(rowsA / 64) * 64 * std::ceil(rowsB / 64) * 64 *
-                        std::max(std::ldexp(1.0, nd.kb), 16.0);
+    nd.swapped = (rowsR < rowsL && rowsR < 64) ? 1 : 0;
+    const double rows = nd.swapped ? rowsR : rowsL;
+    const double cols = nd.swapped ? rowsL : rowsR;
+    nd.tile = rows <= 32 ? 1 : 0;
+    int bm = 0, bn = 0;
+    mfma_tile_shape(nd.tile, &bm, &bn);
+    const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
+                        std::max(std::ldexp(1.0, nd.kb), double(16));
     nd.kernel = XEB_KERNEL_GENERIC;
-    if (!o.force_generic && rowsA >= 32 && rowsB >= 32 && useful >= 65536.0 &&
-        4 * useful >= work && pairs <= double(1 << 26)) {
+    if (!o.force_generic && nd.kb >= 1 && rows >= 8 && cols >= 32 && useful >= 65536.0 &&
+        8 * useful >= work && pairs <= double(1 << 26)) {
       nd.kernel = XEB_KERNEL_MFMA;
+      // Epilogue write order: tile bits sorted by the output position they
+      // feed; bits that select variants come last (columns before rows).
+      const int kmb = nd.swapped ? nd.nb : nd.mb, knb = nd.swapped ? nd.mb : nd.nb;
+      const int8_t* kpm = nd.swapped ? nd.posN : nd.posM;
+      const int8_t* kpn = nd.swapped ? nd.posM : nd.posN;
+      std::vector<std::pair<int, int>> keyed;  // (key, code)
+      for (int j = 0; (1 << j) < bm; ++j) keyed.push_back({j < kmb ? int(kpm[j]) : 2000 + j, j});
+      for (int j = 0; (1 << j) < bn; ++j)
+        keyed.push_back({j < knb ? int(kpn[j]) : 1000 + j, 32 + j});
+      std::sort(keyed.begin(), keyed.end());
+      for (size_t b2 = 0; b2 < keyed.size(); ++b2) nd.ubit[b2] = int8_t(keyed[b2].second);
       nd.pair_mode = (nd.nvar == a.nvar * b.nvar) ? 0 : 1;
       if (nd.pair_mode == 1) {
         nd.pairs.assign(size_t(a.nvar * b.nvar), -1);
@@ -392,6 +411,76 @@ void bind_plan(Plan* p, void* dev, uint64_t bytes) {
   for (Node& nd : p->nodes) nd.valid = false;
 }
 
+Plan::~Plan() {
+  for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+  for (ProfRecord& r : prof) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+}
+
+namespace {
+
+hipEvent_t take_event(Plan* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hip_check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void recycle_records(Plan* p) {
+  for (ProfRecord& r : p->prof) {
+    p->event_pool.push_back(r.start);
+    p->event_pool.push_back(r.stop);
+  }
+  p->prof.clear();
+}
+
+// Records an event pair around `launch` when profiling is on.
+template <class F>
+void timed(Plan* p, hipStream_t stream, int kernel, double cmacs, double bytes, F&& launch) {
+  if (!p->profiling) {
+    launch();
+    return;
+  }
+  ProfRecord r{take_event(p), take_event(p), kernel, cmacs, bytes};
+  hip_check(hipEventRecord(r.start, stream), "hipEventRecord");
+  launch();
+  hip_check(hipEventRecord(r.stop, stream), "hipEventRecord");
+  p->prof.push_back(r);
+}
+
+}  // namespace
+
+void set_profiling(Plan* p, bool on) {
+  DeviceGuard g(p->opt.device);
+  if (!p->prof.empty()) {
+    for (ProfRecord& r : p->prof) hip_check(hipEventSynchronize(r.stop), "hipEventSynchronize");
+    recycle_records(p);
+  }
+  p->profiling = on;
+}
+
+xeb_kernel_profile_t read_profile(Plan* p, int kernel) {
+  DeviceGuard g(p->opt.device);
+  xeb_kernel_profile_t out{};
+  for (ProfRecord& r : p->prof) {
+    if (r.kernel != kernel) continue;
+    hip_check(hipEventSynchronize(r.stop), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, r.start, r.stop), "hipEventElapsedTime");
+    out.launches += 1;
+    out.seconds += double(ms) * 1e-3;
+    out.cmacs += r.cmacs;
+    out.bytes += r.bytes;
+  }
+  return out;
+}
+
 namespace {
 
 const float2* node_ptr(const Plan* p, int id, int64_t sigma) {
@@ -428,32 +517,43 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
       const Node& na = p->nodes[nd.left];
       const Node& nb = p->nodes[nd.right];
       ContractArgs a{};
-      a.A = node_ptr(p, nd.left, sigma);
-      a.B = node_ptr(p, nd.right, sigma);
+      const bool sw = nd.kernel == XEB_KERNEL_MFMA && nd.swapped;
+      a.A = node_ptr(p, sw ? nd.right : nd.left, sigma);
+      a.B = node_ptr(p, sw ? nd.left : nd.right, sigma);
       a.C = reinterpret_cast<float2*>(ws + nd.off_table);
       a.nvar = nd.nvar;
-      a.nvarA = na.nvar;
-      a.nvarB = nb.nvar;
-      a.mb = nd.mb;
-      a.nb = nd.nb;
+      a.nvarA = sw ? nb.nvar : na.nvar;
+      a.nvarB = sw ? na.nvar : nb.nvar;
+      a.mb = sw ? nd.nb : nd.mb;
+      a.nb = sw ? nd.mb : nd.nb;
       a.kb = nd.kb;
       a.pair_mode = nd.pair_mode;
-      std::memcpy(a.posM, nd.posM, sizeof(a.posM));
-      std::memcpy(a.posN, nd.posN, sizeof(a.posN));
+      a.swapped = sw ? 1 : 0;
+      a.tile = nd.tile;
+      std::memcpy(a.posM, sw ? nd.posN : nd.posM, sizeof(a.posM));
+      std::memcpy(a.posN, sw ? nd.posM : nd.posN, sizeof(a.posN));
+      std::memcpy(a.ubit, nd.ubit, sizeof(a.ubit));
+      const double cmacs = double(nd.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
+      const double bytes = 8.0 * (double(na.nvar) * na.size() + double(nb.nvar) * nb.size() +
+                                  double(nd.nvar) * nd.size());
       if (nd.kernel == XEB_KERNEL_MFMA) {
         a.pairs = nd.pair_mode == 1 ? reinterpret_cast<const int32_t*>(ws + nd.off_pairs) : nullptr;
-        launch_contract_mfma(a, stream);
+        timed(p, stream, XEB_KERNEL_MFMA, cmacs, bytes, [&] { launch_contract_mfma(a, stream); });
       } else {
         a.lidx = reinterpret_cast<const int32_t*>(ws + nd.off_lidx);
         a.ridx = reinterpret_cast<const int32_t*>(ws + nd.off_ridx);
-        launch_contract_generic(a, stream);
+        timed(p, stream, XEB_KERNEL_GENERIC, cmacs, bytes,
+              [&] { launch_contract_generic(a, stream); });
       }
       hip_check(hipGetLastError(), "contraction launch");
       nd.valid = true;
       nd.cur_key = key;
     }
-    launch_accumulate(node_ptr(p, p->root, sigma), rho, static_cast<double2*>(amps), comp, p->k,
-                      stream);
+    const double acc_bytes = double(p->k) * (8.0 + 4.0 + 2 * 16.0 + 2 * 16.0);
+    timed(p, stream, XEB_KERNEL_ACCUMULATE, 0.0, acc_bytes, [&] {
+      launch_accumulate(node_ptr(p, p->root, sigma), rho, static_cast<double2*>(amps), comp, p->k,
+                        stream);
+    });
     hip_check(hipGetLastError(), "accumulate launch");
   }
   launch_fold_compensation(static_cast<double2*>(amps), comp, p->k, stream);

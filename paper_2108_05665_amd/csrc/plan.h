@@ -29,6 +29,9 @@ struct Node {
   std::vector<int32_t> lidx, ridx;  // child variants of each variant
   int kernel = XEB_KERNEL_GENERIC;
   int pair_mode = 0;                // MFMA: 0 dense, 1 table
+  int swapped = 0;                  // MFMA: right child supplies the tile rows
+  int tile = 0;                     // MFMA tile shape (see ContractArgs::tile)
+  int8_t ubit[16] = {};             // MFMA epilogue write order
   std::vector<int32_t> pairs;       // MFMA table mode: nvarL * nvarR entries
   int8_t posM[kMaxBits] = {};
   int8_t posN[kMaxBits] = {};
@@ -39,6 +42,12 @@ struct Node {
   uint64_t cur_key = 0;
 
   int64_t size() const { return int64_t(1) << legs.size(); }
+};
+
+struct ProfRecord {
+  hipEvent_t start, stop;
+  int kernel;
+  double cmacs, bytes;
 };
 
 struct Plan {
@@ -57,6 +66,11 @@ struct Plan {
   void* ws = nullptr;
   uint64_t ws_size = 0;
   xeb_stats_t stats{};
+  // Profiling (HIP events around launches).
+  bool profiling = false;
+  std::vector<ProfRecord> prof;      // records of the current profiling window
+  std::vector<hipEvent_t> event_pool;
+  ~Plan();
 };
 
 void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bitstrings, int64_t k,
@@ -67,6 +81,8 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
 double fidelity_plan(Plan* p, const void* amps, hipStream_t stream);
 
 void hip_check(hipError_t e, const char* what);
+void set_profiling(Plan* p, bool on);
+xeb_kernel_profile_t read_profile(Plan* p, int kernel);
 
 }  // namespace xeb
 

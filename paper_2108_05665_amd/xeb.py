@@ -104,6 +104,17 @@ class NodeStats(ctypes.Structure):
     ]
 
 
+class KernelProfile(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("cmacs", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
+KERNEL_IDS = {"generic": 0, "mfma": 1, "accumulate": 2}
+
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _SIG = {
@@ -120,6 +131,8 @@ _SIG = {
     "xeb_fidelity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "xeb_plan_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "xeb_plan_node_stats": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeStats)]),
+    "xeb_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "xeb_plan_read_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(KernelProfile)]),
     "xeb_plan_destroy": (ctypes.c_int, [_P]),
 }
 for _name, (_res, _args) in _SIG.items():
@@ -272,6 +285,15 @@ class Plan:
         st = self.stats()
         L = int(st["n_leaves"])
         return [dict(node=L + i, **self.node_stats(L + i)) for i in range(int(st["n_internal"]))]
+
+    # -- measurement -------------------------------------------------------------
+    def set_profiling(self, enable: bool) -> None:
+        _check(_lib.xeb_plan_set_profiling(self._h, int(bool(enable))))
+
+    def read_profile(self, kernel: str) -> dict:
+        pr = KernelProfile()
+        _check(_lib.xeb_plan_read_profile(self._h, KERNEL_IDS[kernel], ctypes.byref(pr)))
+        return {name: getattr(pr, name) for name, _ in KernelProfile._fields_}
 
     def close(self):
         if self._h:
