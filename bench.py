@@ -3,12 +3,17 @@
 Workload (36 qubits): a 6x6 grid circuit with 12 cycles of sqrt(X)/sqrt(Y)/
 sqrt(W) layers and fSim(pi/2, pi/6) couplers in the ABCDCDAB order plus a
 closing layer, 10^4 seeded bitstrings whose qubits 0..19 share one fixed
-value (the rest uniform), sliced over 10 legs (2^10 slices), complex64.
+value (the rest uniform), sliced over 10 legs (2^10 slices).
 
 A step is one pass of the whole hot path over the batch: every slice's
 contraction with the memo tables (all 2^10 slices), the FP64 cross-slice sum
 and the XEB reduction.  Planning (tree, slicing, plan compilation) happens
 once before the timed region and is reported separately.
+
+Both forms run: split-FP16 MFMA products (the headline `value`) and plain
+complex64 on FP32 MFMA, with the speedup and the split-vs-c64 amplitude and
+XEB differences over all strings, and sampled per-slice partials checked
+against the FP64 oracle for each form.
 
 Prints one JSON line.  Progress goes to stderr.
 """
@@ -17,7 +22,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,21 +30,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "medium_6x6_m12"
-FP32_MFMA_PEAK_TFLOPS = 157.3
+PEAK_TFLOPS = {"c64": 157.3, "split_fp16": 2516.6, "split_bf16": 2516.6}  # dense MFMA
+ISSUED_PER_CMAC = {"c64": 8.0, "split_fp16": 24.0, "split_bf16": 24.0}   # real FLOPs issued
 HBM_PEAK_GBS = 8000.0
+DTYPE = {"c64": "c64 (f32 MFMA)", "split_fp16": "f16 hi/lo split, f32 acc",
+         "split_bf16": "bf16 hi/lo split, f32 acc"}
 METRIC = "amplitudes/sec + contraction TFLOP/s (%MFMA peak), FP16-split vs c64 at stated err"
+ERR_BOUND = {"c64": 1e-5, "split_fp16": 1e-3, "split_bf16": 1e-3}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(circ, strings, sliced, budget_s: float):
+def cpu_baseline(net, pairs, strings, sliced, budget_s: float):
     """The FP64 oracle timed on the host on a bounded sample: full partial
     amplitudes (one string, one slice each) until about `budget_s` seconds of
     contraction time; amplitudes/s = partials/s / 2^s."""
     from oracle import tn
-    from oracle.network import build_network
 
     try:
         from threadpoolctl import threadpool_info
@@ -48,8 +55,6 @@ def cpu_baseline(circ, strings, sliced, budget_s: float):
         cores = max((int(x.get("num_threads", 1)) for x in threadpool_info()), default=1)
     except Exception:
         cores = os.cpu_count() or 1
-    net = build_network(circ)
-    pairs = tn.search_order(tn.closed_leg_sets(net, sliced), trials=64)[0]
     done = 0
     t0 = time.perf_counter()
     while True:
@@ -61,9 +66,8 @@ def cpu_baseline(circ, strings, sliced, budget_s: float):
         if el >= budget_s or done >= 64:
             break
     per_partial = el / done
-    value = 1.0 / (per_partial * (1 << len(sliced)))
     return {
-        "value": value,
+        "value": 1.0 / (per_partial * (1 << len(sliced))),
         "unit": "amplitudes/s",
         "cores": cores,
         "kind": "oracle",
@@ -72,16 +76,40 @@ def cpu_baseline(circ, strings, sliced, budget_s: float):
     }
 
 
+def roofline(prof: dict, prec: str) -> dict:
+    mf = prof["mfma"]
+    if mf["seconds"] <= 0:
+        return {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None}
+    issued = ISSUED_PER_CMAC[prec] * mf["cmacs"]
+    tflops = issued / mf["seconds"] / 1e12
+    gbs = mf["bytes"] / mf["seconds"] / 1e9
+    ai = issued / mf["bytes"]
+    ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if ai >= ridge:
+        r = {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+             "frac": tflops / PEAK_TFLOPS[prec]}
+    else:
+        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": gbs / HBM_PEAK_GBS}
+    r.update({"traffic": None, "kernel": "k_contract_mfma",
+              "launches": mf["launches"], "avg_launch_us": 1e6 * mf["seconds"] / max(mf["launches"], 1),
+              "issued_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
+              "issued_tflops": tflops, "gbs": gbs})
+    return r
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trials", type=int, default=16, help="planner trials")
+    ap.add_argument("--precisions", default="split_fp16,c64",
+                    help="comma list; the first one gives `value`")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slices", type=int, default=None,
-                    help="contract only the first N slices per step (profiling runs)")
+    ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -96,104 +124,136 @@ def main() -> int:
     from paper_2108_05665_amd import planner, xeb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     circ = config_circuit(WORKLOAD)
     strings = config_bitstrings(WORKLOAD, circ.n_qubits)
     t0 = time.perf_counter()
     children, sliced, info = planner.plan(circ, strings, n_sliced=10, trials=args.trials, seed=0)
     t_tree = time.perf_counter() - t0
     log(f"planned tree in {t_tree:.1f} s: cost {info['cost']:.3e} cmacs, max 2^{info['max_log2']}")
-    t0 = time.perf_counter()
-    plan = xeb.Plan(circ, strings, children, sliced, device=0)
-    t_plan = time.perf_counter() - t0
-    st = plan.stats()
     n_slices = 1 << len(sliced)
-    run_slices = n_slices if args.slices is None else min(args.slices, n_slices)
-    log(f"plan compiled in {t_plan:.1f} s, workspace {st['workspace_bytes'] / 2**30:.2f} GiB")
-    amps = plan.new_amps()
 
-    def step():
-        amps.zero_()
-        plan.contract(amps, 0, run_slices)
-        return plan.fidelity(amps)  # waits for the stream
+    oracle_net = oracle_pairs = None
+    if not (args.no_oracle_check and args.no_cpu_baseline):
+        from oracle import tn
+        from oracle.network import build_network
 
-    for w in range(args.warmup):
-        F = step()
-        log(f"warmup {w + 1}/{args.warmup} done, F = {F:.6f}")
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        F = step()
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate")}
-    plan.set_profiling(False)
+        oracle_net = build_network(circ)
+        oracle_pairs = tn.search_order(tn.closed_leg_sets(oracle_net, sliced), trials=64)[0]
+    check_sigma, check_idx = 777, [0, 4321, 9999]
+    oracle_ref = None
+    if not args.no_oracle_check:
+        from oracle import tn
 
-    sec_per_step = elapsed / args.steps
-    frac_slices = run_slices / n_slices
-    amps_per_s = len(strings) * frac_slices / sec_per_step
-    cm = st["cmacs_full"] * frac_slices if run_slices == n_slices else None
-    if cm is None:
-        cm = sum(p["cmacs"] for p in prof.values()) / args.steps
-    useful_tflops = 8.0 * cm / sec_per_step / 1e12
-    mf = prof["mfma"]
-    mfma_tflops = 8.0 * mf["cmacs"] / mf["seconds"] / 1e12 if mf["seconds"] > 0 else 0.0
-    mfma_gbs = mf["bytes"] / mf["seconds"] / 1e9 if mf["seconds"] > 0 else 0.0
-    ai = 8.0 * mf["cmacs"] / mf["bytes"] if mf["bytes"] > 0 else 0.0
-    ridge = FP32_MFMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if ai >= ridge:
-        roof = {"bound": "mfma", "achieved": mfma_tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": mfma_tflops / FP32_MFMA_PEAK_TFLOPS}
-    else:
-        roof = {"bound": "hbm", "achieved": mfma_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": mfma_gbs / HBM_PEAK_GBS}
-    roof.update({"kernel": "k_contract_mfma", "traffic": None,
-                 "launches_per_step": mf["launches"] / args.steps,
-                 "flops_per_launch": 8.0 * mf["cmacs"] / max(mf["launches"], 1),
-                 "bytes_per_launch": mf["bytes"] / max(mf["launches"], 1),
-                 "avg_launch_us": 1e6 * mf["seconds"] / max(mf["launches"], 1),
-                 "arith_intensity_flop_per_byte": ai})
-    kernel_share = {name: p["seconds"] / args.steps / sec_per_step for name, p in prof.items()}
+        oracle_ref = np.array([tn.partial_amplitude(oracle_net, int(strings[i]), sliced, check_sigma,
+                                                    pairs=oracle_pairs) for i in check_idx])
+        log("oracle partials for the sampled check done")
 
+    results = {}
+    for prec in precs:
+        t0 = time.perf_counter()
+        plan = xeb.Plan(circ, strings, children, sliced, device=0, precision=prec)
+        t_plan = time.perf_counter() - t0
+        st = plan.stats()
+        amps = plan.new_amps()
+
+        def step():
+            amps.zero_()
+            plan.contract(amps)
+            return plan.fidelity(amps)  # waits for the stream
+
+        for w in range(args.warmup):
+            F = step()
+            log(f"{prec}: warmup {w + 1}/{args.warmup} done, F = {F:.6f}")
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            F = step()
+            log(f"{prec}: step {k + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate")}
+        plan.set_profiling(False)
+        final = amps.cpu().numpy()
+        sampled_err = None
+        if oracle_ref is not None:
+            part = plan.new_amps()
+            plan.contract(part, check_sigma, check_sigma + 1)
+            got = part.cpu().numpy()[check_idx]
+            sampled_err = float(np.linalg.norm(got - oracle_ref) / np.linalg.norm(oracle_ref))
+        sec = elapsed / args.steps
+        results[prec] = dict(
+            sec=sec, F=F, amps=final, prof=prof, st=st, t_plan=t_plan, sampled_err=sampled_err,
+            amps_per_s=len(strings) / sec,
+            useful_tflops=8.0 * st["cmacs_full"] / sec / 1e12,
+            share={n: p["seconds"] / args.steps / sec for n, p in prof.items()},
+        )
+        log(f"{prec}: {1e3 * sec:.0f} ms/step, {len(strings) / sec:.0f} amplitudes/s, "
+            f"sampled oracle err {sampled_err}")
+        plan.close()
+        del amps
+
+    head = precs[0]
+    r = results[head]
+    ref_prec = "c64" if "c64" in results else None
+    compare = {}
+    for prec, x in results.items():
+        if ref_prec and prec != ref_prec:
+            a, b = x["amps"], results[ref_prec]["amps"]
+            compare[prec] = {
+                "speedup_vs_c64": results[ref_prec]["sec"] / x["sec"],
+                "amp_rel_diff_vs_c64_all_strings": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                "xeb_abs_diff_vs_c64": abs(x["F"] - results[ref_prec]["F"]),
+            }
+    forms = {
+        prec: {
+            "amplitudes_per_s": x["amps_per_s"], "ms_per_step": 1e3 * x["sec"],
+            "contraction_tflops_useful": x["useful_tflops"],
+            "mfma_frac_useful": x["useful_tflops"] * ISSUED_PER_CMAC[prec] / 8.0 / PEAK_TFLOPS[prec],
+            "xeb": x["F"], "sampled_oracle_rel_err": x["sampled_err"],
+            "err_bound": ERR_BOUND[prec], "kernel_time_share": x["share"],
+            "roofline": roofline(x["prof"], prec), "plan_compile_s": x["t_plan"],
+            **compare.get(prec, {}),
+        }
+        for prec, x in results.items()
+    }
+    st = r["st"]
     out = {
         "metric": METRIC,
-        "value": amps_per_s,
+        "value": r["amps_per_s"],
         "unit": "amplitudes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec_per_step,
+        "ms_per_step": 1e3 * r["sec"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": DTYPE[head],
         "data": "synthetic",
         "config": {
             "workload": f"{WORKLOAD}: 36 qubits on a 6x6 grid, 12 cycles (ABCDCDAB + closing "
-                        "layer), 10^4 strings with qubits 0-19 fixed, 2^10 slices, complex64",
+                        "layer), 10^4 strings with qubits 0-19 fixed, 2^10 slices",
             "strings": int(len(strings)),
             "distinct_strings": int(st["k_distinct"]),
             "slices": n_slices,
-            "slices_per_step": run_slices,
-            "precision": "c64",
+            "precision": head,
         },
-        "contraction_tflops_useful": useful_tflops,
-        "mfma_frac_useful": useful_tflops / FP32_MFMA_PEAK_TFLOPS,
-        "kernel_time_share": kernel_share,
-        "plan": {"tree_s": t_tree, "compile_s": t_plan, "cmacs_full": st["cmacs_full"],
+        "contraction_tflops_useful": r["useful_tflops"],
+        "roofline": roofline(r["prof"], head),
+        "forms": forms,
+        "plan": {"tree_s": t_tree, "cmacs_full": st["cmacs_full"],
                  "cmacs_unsliced_tree": info["unsliced_cost"], "max_log2": info["max_log2"],
-                 "workspace_gib": st["workspace_bytes"] / 2**30, "sum_variants": st["sum_variants"],
-                 "evals_full": st["evals_full"]},
-        "xeb": F,
-        "roofline": roof,
+                 "estimated_s": info.get("seconds"), "workspace_gib": st["workspace_bytes"] / 2**30,
+                 "sum_variants": st["sum_variants"], "evals_full": st["evals_full"]},
+        "xeb": r["F"],
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(circ, strings, sliced, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(oracle_net, oracle_pairs, strings, sliced, args.cpu_budget)
     print(json.dumps(out), flush=True)
-    plan.close()
     return 0
 
 

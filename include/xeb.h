@@ -52,9 +52,19 @@ extern "C" {
 typedef struct xeb_plan* xeb_plan_t;
 
 /* ---- precision of the contraction kernels ------------------------------ */
-#define XEB_PREC_C64 0         /* complex64, FP32 MFMA, FP32 accumulation */
-#define XEB_PREC_SPLIT_FP16 1  /* reserved: hi/lo FP16 operands, FP32 accumulation */
-#define XEB_PREC_SPLIT_BF16 2  /* reserved: hi/lo BF16 operands, FP32 accumulation */
+/*
+ * Tables are complex64 in HBM in every mode; the precision selects how the
+ * MFMA contractions multiply (the generic kernel always works in FP32):
+ *   C64: FP32 MFMA (v_mfma_f32_32x32x2f32 / 16x16x4f32), FP32 accumulation.
+ *   SPLIT_FP16: each operand float x, scaled by a power of two 2^e chosen from
+ *     the tensor's largest magnitude, is split into hi = fp16(x 2^e) and
+ *     lo = fp16(x 2^e - hi); hi.hi + hi.lo + lo.hi accumulate in FP32 on FP16
+ *     MFMA (lo.lo dropped); the result is scaled back by 2^-(eA+eB).
+ *   SPLIT_BF16: the same with bf16 halves and no scale.
+ */
+#define XEB_PREC_C64 0
+#define XEB_PREC_SPLIT_FP16 1
+#define XEB_PREC_SPLIT_BF16 2
 
 /*
  * A circuit: gates in time order.
@@ -113,19 +123,23 @@ typedef struct {
   double rw_elems_full;      /* elements read+written by all contractions, all slices */
   double evals_full;         /* node evaluations (kernel launches) for all slices */
   uint64_t workspace_bytes;
+  int64_t n_blocks;          /* string blocks chosen by the dry run (1 = all strings at once) */
 } xeb_stats_t;
 
 #define XEB_KERNEL_GENERIC 0  /* per-element kernel (small or sparse nodes) */
 #define XEB_KERNEL_MFMA 1     /* FP32-MFMA stacked GEMM */
 
+/* Per internal node; key counts are summed over the string blocks (with one
+ * block, `variants` is the node's exact evaluation count |t_T| per slice). */
 typedef struct {
   int32_t left, right;       /* child node ids */
-  int64_t variants;          /* |t_T|: distinct string keys of this node */
+  int64_t variants;          /* distinct string keys of this node */
   int64_t left_variants, right_variants;
   int32_t m_bits, n_bits, k_bits; /* free legs of left, free legs of right, shared legs */
   uint64_t slice_mask;       /* bit j set: the node depends on sliced leg j */
-  int32_t kernel;            /* XEB_KERNEL_* */
+  int32_t kernel;            /* XEB_KERNEL_* (first block) */
   int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
+  int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256 */
   double cmacs_per_eval;     /* |t_T| 2^(q+r) */
 } xeb_node_stats_t;
 
@@ -186,6 +200,12 @@ int xeb_network_describe(const xeb_circuit_t* circuit, int32_t fuse_1q, int32_t 
 int xeb_plan_create(const xeb_circuit_t* circuit, const uint64_t* bitstrings, int64_t k,
                     const xeb_tree_t* contraction_tree, const int32_t* sliced_legs, int32_t s,
                     const xeb_options_t* opt, xeb_plan_t* out);
+/* Memory: every node keeps the table of all its keys among the strings being
+ * contracted.  When opt->memory_budget is set and that does not fit, the
+ * distinct strings, sorted in the lexicographic tuple order of Appendix C,
+ * are cut into 2, 4, 8, ... contiguous blocks contracted one after another
+ * (a block's keys share the left spine, as in eval'); the first count that
+ * fits is kept (xeb_stats_t.n_blocks). */
 
 /* Device bytes the plan needs (from the dry run). */
 int xeb_plan_workspace_bytes(xeb_plan_t plan, uint64_t* bytes);
@@ -255,6 +275,32 @@ typedef struct {
 } xeb_kernel_profile_t;
 int xeb_plan_set_profiling(xeb_plan_t plan, int32_t enable);
 int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t* out);
+/* The same sums restricted to the launches of one internal node (any kernel). */
+int xeb_plan_read_node_profile(xeb_plan_t plan, int32_t node, xeb_kernel_profile_t* out);
+
+/*
+ * Batched form: several bound plans (different circuits, uneven sizes) as one
+ * hipGraph.  xeb_batch_create captures, for every plan, the clearing of its
+ * amplitude buffer, the contraction of all its 2^s slices (as xeb_contract
+ * over [0, 2^s)) and its XEB reduction, each plan on its own forked capture
+ * stream (the plans share nothing), and instantiates the graph.  Every
+ * xeb_batch_launch replays the whole batch with one hipGraphLaunch on
+ * `stream`; afterwards each amplitude buffer holds its complete amplitudes
+ * (a launch overwrites, it does not accumulate).
+ *   plans (host) [n]: bound plans on one device, each listed once, n >= 1.
+ *   amps (host) [n]: device complex128 [k_i] buffers, caller-owned; their
+ *     addresses are captured, so they must stay valid while the batch lives.
+ * xeb_batch_fidelities waits for `stream` and writes each plan's F (host
+ * double [n]; NaN for a plan with k = 0).
+ * The plans must not be used by other calls while a launch is in flight;
+ * eager calls between launches are fine.
+ * Errors: XEB_EINVAL, XEB_ESTATE (a plan without workspace), XEB_EHIP.
+ */
+typedef struct xeb_batch* xeb_batch_t;
+int xeb_batch_create(const xeb_plan_t* plans, void* const* amps, int32_t n, xeb_batch_t* out);
+int xeb_batch_launch(xeb_batch_t batch, void* stream);
+int xeb_batch_fidelities(xeb_batch_t batch, void* stream, double* F);
+int xeb_batch_destroy(xeb_batch_t batch);
 
 /* Release the plan's host memory (the workspace stays the caller's). */
 int xeb_plan_destroy(xeb_plan_t plan);

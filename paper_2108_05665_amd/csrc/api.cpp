@@ -1,9 +1,11 @@
 // C ABI entry points (xeb.h): argument checks, error capture, no exceptions
 // across the boundary.
 
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "plan.h"
 #include "xeb.h"
@@ -145,16 +147,24 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     std::memset(st, 0, sizeof(*st));
     st->left = nd.left;
     st->right = nd.right;
-    st->variants = nd.nvar;
-    st->left_variants = p.nodes[nd.left].nvar;
-    st->right_variants = p.nodes[nd.right].nvar;
+    auto keys = [&](int id) -> int64_t {
+      if (p.nodes[id].leaf) return p.nodes[id].leaf_nvar * int64_t(p.blocks.size());
+      int64_t t = 0;
+      for (const xeb::Block& b : p.blocks) t += b.nodes[id - p.n_leaves].nvar;
+      return t;
+    };
+    st->variants = keys(node);
+    st->left_variants = keys(nd.left);
+    st->right_variants = keys(nd.right);
     st->m_bits = nd.mb;
     st->n_bits = nd.nb;
     st->k_bits = nd.kb;
     st->slice_mask = nd.smask;
-    st->kernel = nd.kernel;
-    st->swapped = nd.kernel == XEB_KERNEL_MFMA ? nd.swapped : 0;
-    st->cmacs_per_eval = double(nd.nvar) * double(uint64_t(1) << (nd.mb + nd.nb + nd.kb));
+    const xeb::NodeBlock& nb = p.blocks.front().nodes[node - p.n_leaves];
+    st->kernel = nb.kernel;
+    st->swapped = nb.kernel == XEB_KERNEL_MFMA ? nb.swapped : 0;
+    st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : -1;
+    st->cmacs_per_eval = double(st->variants) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   });
 }
 
@@ -166,7 +176,56 @@ int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t*
   return guarded([&] {
     if (!out) xeb::fail(XEB_EINVAL, "out is NULL");
     if (kernel < 0 || kernel > XEB_KERNEL_ACCUMULATE) xeb::fail(XEB_EINVAL, "unknown kernel class");
-    *out = xeb::read_profile(&impl(plan), kernel);
+    *out = xeb::read_profile(&impl(plan), kernel, -1);
+  });
+}
+
+int xeb_plan_read_node_profile(xeb_plan_t plan, int32_t node, xeb_kernel_profile_t* out) {
+  return guarded([&] {
+    xeb::Plan& p = impl(plan);
+    if (!out) xeb::fail(XEB_EINVAL, "out is NULL");
+    if (node < p.n_leaves || node >= int32_t(p.nodes.size()))
+      xeb::fail(XEB_EINVAL, "node is not an internal node id");
+    *out = xeb::read_profile(&p, -1, node);
+  });
+}
+
+int xeb_batch_create(const xeb_plan_t* plans, void* const* amps, int32_t n, xeb_batch_t* out) {
+  return guarded([&] {
+    if (!out) xeb::fail(XEB_EINVAL, "output handle pointer is NULL");
+    *out = nullptr;
+    if (!plans || n < 1) xeb::fail(XEB_EINVAL, "a batch needs at least one plan");
+    std::vector<xeb::Plan*> ps(n);
+    for (int i = 0; i < n; ++i) ps[i] = &impl(plans[i]);
+    xeb_batch* b = new xeb_batch();
+    try {
+      b->impl = xeb::create_batch(ps.data(), amps, n);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+int xeb_batch_launch(xeb_batch_t batch, void* stream) {
+  return guarded([&] {
+    if (!batch) xeb::fail(XEB_EINVAL, "batch handle is NULL");
+    xeb::launch_batch(batch->impl, static_cast<hipStream_t>(stream));
+  });
+}
+
+int xeb_batch_fidelities(xeb_batch_t batch, void* stream, double* F) {
+  return guarded([&] {
+    if (!batch) xeb::fail(XEB_EINVAL, "batch handle is NULL");
+    xeb::batch_fidelities(batch->impl, static_cast<hipStream_t>(stream), F);
+  });
+}
+
+int xeb_batch_destroy(xeb_batch_t batch) {
+  return guarded([&] {
+    if (batch) xeb::destroy_batch(batch->impl);
+    delete batch;
   });
 }
 

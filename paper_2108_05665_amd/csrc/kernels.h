@@ -27,23 +27,35 @@ struct ContractArgs {
   int32_t mb, nb, kb;
   int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table
   int32_t swapped;       // MFMA: rows are R's variants (A <- R, B <- L)
-  int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128
+  int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128, 2 = 16 x 256
   int8_t posM[kMaxBits];
   int8_t posN[kMaxBits];
   // MFMA epilogue write order: bit b of an element's number inside the tile is
   // row bit ubit[b] (< 32) or column bit ubit[b] - 32.
   int8_t ubit[16];
+  int32_t prec;          // MFMA operand precision: XEB_PREC_C64 / _SPLIT_FP16 / _SPLIT_BF16
+  // Largest |re|, |im| of the operand tables (float bits), read for the FP16
+  // scale.  The output's is published as atomicMax((epoch << 32) | bits) into
+  // amax_out, so the latest evaluation (largest epoch) wins without clearing
+  // the slot between evaluations.  NULL: not tracked.
+  const uint32_t* amaxA;
+  const uint32_t* amaxB;
+  unsigned long long* amax_out;
+  uint32_t epoch;
 };
 
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
 void mfma_tile_shape(int tile, int* bm, int* bn);
+// Queries (once per device) the occupancy the persistent grids use, so that a
+// later stream capture makes no occupancy call.
+void prepare_mfma_launch(int prec);
 
 // Cross-slice accumulation (Appendix A, "Slicing": sum over assignments) in
-// FP64 with Neumaier compensation: amps[i] += partial[rho[i]].
+// FP64 with Neumaier compensation: amps[idx[j]] += partial[rho[j]], j < n.
 void launch_zero(void* p, uint64_t bytes, hipStream_t s);
-void launch_accumulate(const float2* partial, const int32_t* rho, double2* amps, double2* comp,
-                       int64_t k, hipStream_t s);
+void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
+                       double2* amps, double2* comp, int64_t n, hipStream_t s);
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s);
 
 // Linear XEB (Eq. 1): out[0] = 2^n / k * sum |amps|^2 - 1.

@@ -30,7 +30,18 @@ __device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int nbi
 
 // ---------------------------------------------------------------------------
 // Generic contraction.
+// Largest |re|, |im| of a wave's values -> one atomicMax per wave on
+// (epoch << 32) | float bits (non-negative floats order like their bits; a
+// later evaluation's larger epoch replaces older values).
+__device__ __forceinline__ void publish_amax(float v, unsigned long long* slot, uint32_t epoch) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(slot, (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(v));
+}
+
 __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
+  float amax = 0.f;
   const int mn = g.mb + g.nb;
   const int64_t per = int64_t(1) << mn;
   const int64_t total = g.nvar * per;
@@ -47,49 +58,150 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
     const float2* pa = g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb);
     const float2* pb = g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb);
     float re = 0.f, im = 0.f;
+#pragma unroll 4
     for (int64_t k = 0; k < K; ++k) {
       const float2 x = pa[k], y = pb[k];
       re += x.x * y.x - x.y * y.y;
       im += x.x * y.y + x.y * y.x;
     }
     g.C[a * per + deposit(m, g.posM, g.mb) + deposit(n, g.posN, g.nb)] = make_float2(re, im);
+    amax = fmaxf(amax, fmaxf(fabsf(re), fabsf(im)));
   }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
 
 // ---------------------------------------------------------------------------
-// MFMA contraction.  Workgroup tile BM x BN complex (64 x 64 or 32 x 128), four
-// waves, each one 32 x 32 block of v_mfma_f32_32x32x2f32.  K is staged through
-// LDS TK = 16 complex at a time as separate re / im planes [k][plane][row]
-// (+1 float padding); the next K tile is fetched into registers (16-byte loads,
-// consecutive lanes along one contiguous row) while the current one is
-// multiplied.  The epilogue parks the tile in LDS and writes it out in the
-// order of the output layout's bit positions (ubit), so a wave stores runs of
-// consecutive addresses.
-constexpr int TK = 16, PAD = 1;
+// MFMA contraction (stacked-key complex GEMM  C = A . B^T, both operands with
+// their K legs contiguous).
+//
+// Tile shapes (workgroup of four waves):
+//   0: 64 x 64,  waves 2 x 2, one 32 x 32 block each
+//   1: 32 x 128, waves 1 x 4, one 32 x 32 block each
+//   2: 16 x 256, waves 1 x 4, four 16 x 16 blocks each
+// Precisions:
+//   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
+//     4 real MACs: the instruction's K runs over (re, im) of the row operand
+//     and the column operand supplies (re, -im) for the real part and (im, re)
+//     for the imaginary part.  LDS holds re / im planes [k][plane][row].
+//   PREC 1 / 2 (split FP16 / BF16): each operand float x, scaled by a power of
+//     two 2^e (FP16 only; e from the tensor's largest magnitude so that it lands
+//     in [2^14, 2^15)), becomes hi = round(x 2^e), lo = round(x 2^e - hi); the
+//     products hi.hi + hi.lo + lo.hi accumulate in FP32 on
+//     v_mfma_f32_32x32x16 / 16x16x32 (lo.lo is dropped) and the result is
+//     scaled back by 2^-(eA + eB).  LDS holds hi / lo planes [row][realified k]
+//     with (re, im) interleaved; the column operand's (re, -im) and (im, re)
+//     forms are a sign flip and a 16-bit rotation of each packed pair.
+// K is staged TK = 16 complex at a time.
+//
+// The grid is persistent: each workgroup walks tiles p = blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the register prefetch of the next K slab runs
+// across tile boundaries, so the next tile's first loads overlap the current
+// tile's last MFMAs and its epilogue.  Workgroup w runs on XCD w % 8; the walk
+// is swizzled so that each XCD covers a contiguous range of tiles in
+// column-major order, and tiles sharing one B slab stay in one L2.
+//
+// Epilogue: the tile is parked in LDS and written in the order of the output
+// layout's bit positions (ubit), so each wave stores runs of consecutive
+// addresses.  With FP16 operands the epilogue also publishes the output's
+// largest magnitude for the consumer's scale.
+constexpr int TK = 16, PAD = 1, KH = 2 * TK + 8;  // KH: halves per split LDS row
 
-template <int BM, int BN>
-struct Tile {
-  static constexpr int WM = BM / 32;
+template <int CFG>
+struct Tile;
+template <>
+struct Tile<0> { static constexpr int BM = 64, BN = 64, MF = 32, WM = 2; };
+template <>
+struct Tile<1> { static constexpr int BM = 32, BN = 128, MF = 32, WM = 1; };
+template <>
+struct Tile<2> { static constexpr int BM = 16, BN = 256, MF = 16, WM = 1; };
+
+template <int CFG, int PREC>
+struct TileInfo {
+  using B_ = Tile<CFG>;
+  static constexpr int BM = B_::BM, BN = B_::BN, MF = B_::MF, WM = B_::WM;
   static constexpr int WN = 4 / WM;
-  static_assert(WN * 32 == BN, "four 32x32 wave blocks per tile");
-  static constexpr int A_VEC = BM * TK / 2 / 256;
-  static constexpr int B_VEC = BN * TK / 2 / 256;
-  static constexpr int LDS_A = TK * 2 * (BM + PAD);
-  static constexpr int LDS_MAIN = LDS_A + TK * 2 * (BN + PAD);
+  static constexpr int BMW = BM / WM, BNW = BN / WN;
+  static constexpr int FM = BMW / MF, FN = BNW / MF;
+  static constexpr int REGS = MF == 32 ? 16 : 4;
+  static constexpr int A_F4 = BM * TK / 2;  // float4 loads per tile slab
+  static constexpr int B_F4 = BN * TK / 2;
+  static constexpr int A_VEC = (A_F4 + 255) / 256;
+  static constexpr int B_VEC = (B_F4 + 255) / 256;
+  // LDS, in floats.
+  static constexpr int LDS_A = PREC == 0 ? TK * 2 * (BM + PAD) : BM * KH;  // (hi + lo) / 2
+  static constexpr int LDS_B = PREC == 0 ? TK * 2 * (BN + PAD) : BN * KH;
+  static constexpr int LDS_MAIN = LDS_A + LDS_B;
   static constexpr int LDS_EPI = BM * (BN + 1) * 2;
   static constexpr int LDS = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
-  static constexpr int UBITS = (BM == 64 ? 6 : 5) + (BN == 64 ? 6 : 7);
+  static constexpr int LOG_BM = BM == 64 ? 6 : (BM == 32 ? 5 : 4);
+  static constexpr int LOG_BN = BN == 64 ? 6 : (BN == 128 ? 7 : 8);
+  static constexpr int UBITS = LOG_BM + LOG_BN;
   static constexpr int PER_THREAD = BM * BN / 256;
 };
 
-template <int BM, int BN>
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Scale exponent e with amax 2^e in [2^14, 2^15) (0 for an all-zero tensor).
+__device__ __forceinline__ int fp16_scale_exp(const uint32_t* slot) {
+  const float m = __uint_as_float(*slot);
+  if (!(m > 0.f)) return 0;
+  int e = 14 - ilogbf(m);
+  return e < -120 ? -120 : (e > 120 ? 120 : e);
+}
+
+// Split one float into (hi, lo) 16-bit halves, returned as raw bits.
+template <int PREC>
+__device__ __forceinline__ void split2(float x, uint32_t& hi, uint32_t& lo) {
+  if constexpr (PREC == 1) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  } else {
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+// Two complex numbers (float4) scaled by s -> packed hi and lo halves (uint2
+// each), realified order re0 im0 re1 im1.
+template <int PREC>
+__device__ __forceinline__ void split_store(float4 v, float s, uint16_t* hi_row, uint16_t* lo_row) {
+  uint32_t h[4], l[4];
+  split2<PREC>(v.x * s, h[0], l[0]);
+  split2<PREC>(v.y * s, h[1], l[1]);
+  split2<PREC>(v.z * s, h[2], l[2]);
+  split2<PREC>(v.w * s, h[3], l[3]);
+  *reinterpret_cast<uint2*>(hi_row) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+  *reinterpret_cast<uint2*>(lo_row) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+}
+
+template <int MF, int PREC>
+__device__ __forceinline__ void mma16(const u32x4& a, const u32x4& b, float* acc_raw);
+
+// (re, im) pairs -> (re, -im) and (im, re).
+__device__ __forceinline__ u32x4 conj_im(u32x4 w) { return w ^ 0x80000000u; }
+__device__ __forceinline__ u32x4 swap_pair(u32x4 w) { return (w >> 16) | (w << 16); }
+
+template <int CFG, int PREC>
 __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
-  using T = Tile<BM, BN>;
-  __shared__ float smem[T::LDS];
+  using T = TileInfo<CFG, PREC>;
+  constexpr int BM = T::BM, BN = T::BN, MF = T::MF;
+  typedef float accv __attribute__((ext_vector_type(T::REGS)));
+  __shared__ __attribute__((aligned(16))) float smem[T::LDS];
   __shared__ int64_t dep_m_lo[BM];
   __shared__ int64_t dep_n_lo[BN];
   float(*As)[2][BM + PAD] = reinterpret_cast<float(*)[2][BM + PAD]>(smem);
   float(*Bs)[2][BN + PAD] = reinterpret_cast<float(*)[2][BN + PAD]>(smem + T::LDS_A);
+  // Split layout: hi plane then lo plane, rows of KH halves.
+  uint16_t* Ahi = reinterpret_cast<uint16_t*>(smem);
+  uint16_t* Alo = Ahi + BM * KH;
+  uint16_t* Bhi = reinterpret_cast<uint16_t*>(smem + T::LDS_A);
+  uint16_t* Blo = Bhi + BN * KH;
   float2* Ct = reinterpret_cast<float2*>(smem);
 
   const int tid = threadIdx.x;
@@ -98,8 +210,10 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   const int wm = wave / T::WN, wn = wave % T::WN;
   const int64_t rowsA = g.nvarA << g.mb;
   const int64_t rowsB = g.nvarB << g.nb;
-  const int64_t tiles_n = (rowsB + BN - 1) / BN;
-  const int64_t tiles = tiles_n * ((rowsA + BM - 1) / BM);
+  const int64_t tiles_m = (rowsA + BM - 1) / BM;
+  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  const int64_t per_xcd = (tiles + 7) / 8;
+  const int64_t walk = per_xcd * 8;
   const int64_t K = int64_t(1) << g.kb;
   const int64_t M = int64_t(1) << g.mb;
   const int64_t N = int64_t(1) << g.nb;
@@ -107,10 +221,17 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   const int64_t m_lo_mask = (M < BM ? M : BM) - 1;
   const int64_t n_lo_mask = (N < BN ? N : BN) - 1;
 
+  // Operand scales (FP16 split only) and the output's rescale.
+  int eA = 0, eB = 0;
+  if constexpr (PREC == 1) {
+    eA = fp16_scale_exp(g.amaxA);
+    eB = fp16_scale_exp(g.amaxB);
+  }
+  const float sA = ldexpf(1.f, eA), sB = ldexpf(1.f, eB), s_out = ldexpf(1.f, -(eA + eB));
+  float amax = 0.f;
+
   for (int i = tid; i < BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.posM, g.mb);
   for (int i = tid; i < BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.posN, g.nb);
-  // Row / column inside the tile of this thread's epilogue elements: bits 0..7
-  // of the element number come from tid, the rest from the loop counter.
   int r_tid = 0, c_tid = 0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
@@ -124,83 +245,245 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   }
   __syncthreads();
 
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const int64_t row0 = (tile / tiles_n) * BM;
-    const int64_t col0 = (tile % tiles_n) * BN;
+  // Walk position p -> logical tile (XCD-contiguous, column-major).
+  auto tile_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
+  auto next_p = [&](int64_t p) -> int64_t {
+    for (p += gridDim.x; p < walk; p += gridDim.x)
+      if (tile_of(p) < tiles) return p;
+    return walk;
+  };
 
-    floatx16 acc_re, acc_im;
+  float4 ra[T::A_VEC], rb[T::B_VEC];
+  auto fetch = [&](int64_t tile, int64_t k0) {
+    const int64_t row0 = (tile % tiles_m) * BM;
+    const int64_t col0 = (tile / tiles_m) * BN;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      acc_re[v] = 0.f;
-      acc_im[v] = 0.f;
+    for (int t = 0; t < T::A_VEC; ++t) {
+      const int e = tid + t * 256;
+      const int r = e / (TK / 2), kp = e % (TK / 2);
+      const int64_t gr = row0 + r, gk = k0 + 2 * kp;
+      ra[t] = (e < T::A_F4 && gr < rowsA && gk < K)
+                  ? *reinterpret_cast<const float4*>(g.A + (gr << g.kb) + gk)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+#pragma unroll
+    for (int t = 0; t < T::B_VEC; ++t) {
+      const int e = tid + t * 256;
+      const int r = e / (TK / 2), kp = e % (TK / 2);
+      const int64_t gr = col0 + r, gk = k0 + 2 * kp;
+      rb[t] = (e < T::B_F4 && gr < rowsB && gk < K)
+                  ? *reinterpret_cast<const float4*>(g.B + (gr << g.kb) + gk)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
 
-    float4 ra[T::A_VEC], rb[T::B_VEC];
-    auto fetch = [&](int64_t k0) {
+  int64_t p = blockIdx.x;
+  if (p < walk && tile_of(p) >= tiles) p = next_p(p);
+  if (p >= walk) {
+    if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
+    return;
+  }
+  fetch(tile_of(p), 0);
+
+  while (p < walk) {
+    const int64_t tile = tile_of(p);
+    const int64_t row0 = (tile % tiles_m) * BM;
+    const int64_t col0 = (tile / tiles_m) * BN;
+    const int64_t pn = next_p(p);
+
+    accv acc_re[T::FM][T::FN], acc_im[T::FM][T::FN];
 #pragma unroll
-      for (int t = 0; t < T::A_VEC; ++t) {
-        const int e = tid + t * 256;
-        const int r = e / (TK / 2), kp = e % (TK / 2);
-        const int64_t gr = row0 + r, gk = k0 + 2 * kp;
-        ra[t] = (gr < rowsA && gk < K)
-                    ? *reinterpret_cast<const float4*>(g.A + (gr << g.kb) + gk)
-                    : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+    for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
-      for (int t = 0; t < T::B_VEC; ++t) {
-        const int e = tid + t * 256;
-        const int r = e / (TK / 2), kp = e % (TK / 2);
-        const int64_t gr = col0 + r, gk = k0 + 2 * kp;
-        rb[t] = (gr < rowsB && gk < K)
-                    ? *reinterpret_cast<const float4*>(g.B + (gr << g.kb) + gk)
-                    : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    };
-    fetch(0);
+      for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < T::REGS; ++v) {
+          acc_re[fm][fn][v] = 0.f;
+          acc_im[fm][fn][v] = 0.f;
+        }
+
     for (int64_t k0 = 0; k0 < K; k0 += TK) {
+      // Registers -> LDS.
 #pragma unroll
       for (int t = 0; t < T::A_VEC; ++t) {
         const int e = tid + t * 256;
-        const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
-        As[kk][0][r] = ra[t].x;
-        As[kk][1][r] = ra[t].y;
-        As[kk + 1][0][r] = ra[t].z;
-        As[kk + 1][1][r] = ra[t].w;
+        if (e < T::A_F4) {
+          const int r = e / (TK / 2), kp = e % (TK / 2), kk = 2 * kp;
+          if constexpr (PREC == 0) {
+            As[kk][0][r] = ra[t].x;
+            As[kk][1][r] = ra[t].y;
+            As[kk + 1][0][r] = ra[t].z;
+            As[kk + 1][1][r] = ra[t].w;
+          } else {
+            split_store<PREC>(ra[t], sA, Ahi + r * KH + 4 * kp, Alo + r * KH + 4 * kp);
+          }
+        }
       }
 #pragma unroll
       for (int t = 0; t < T::B_VEC; ++t) {
         const int e = tid + t * 256;
-        const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
-        Bs[kk][0][r] = rb[t].x;
-        Bs[kk][1][r] = rb[t].y;
-        Bs[kk + 1][0][r] = rb[t].z;
-        Bs[kk + 1][1][r] = rb[t].w;
+        if (e < T::B_F4) {
+          const int r = e / (TK / 2), kp = e % (TK / 2), kk = 2 * kp;
+          if constexpr (PREC == 0) {
+            Bs[kk][0][r] = rb[t].x;
+            Bs[kk][1][r] = rb[t].y;
+            Bs[kk + 1][0][r] = rb[t].z;
+            Bs[kk + 1][1][r] = rb[t].w;
+          } else {
+            split_store<PREC>(rb[t], sB, Bhi + r * KH + 4 * kp, Blo + r * KH + 4 * kp);
+          }
+        }
       }
       __syncthreads();
-      if (k0 + TK < K) fetch(k0 + TK);
-      const int i = lane & 31;
-      const int half = lane >> 5;  // 0: real part of the K = 2 pair, 1: imaginary
+      if (k0 + TK < K)
+        fetch(tile, k0 + TK);
+      else if (pn < walk)
+        fetch(tile_of(pn), 0);
+
+      if constexpr (PREC == 0 && MF == 32) {
+        const int i = lane & 31;
+        const int half = lane >> 5;  // 0: real part of the K = 2 pair, 1: imaginary
 #pragma unroll
-      for (int kk = 0; kk < TK; ++kk) {
-        const float a = As[kk][half][wm * 32 + i];
-        const float bre = Bs[kk][0][wn * 32 + i];
-        const float bim = Bs[kk][1][wn * 32 + i];
-        const float b_for_re = half ? -bim : bre;
-        const float b_for_im = half ? bre : bim;
-        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_re, acc_re, 0, 0, 0);
-        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b_for_im, acc_im, 0, 0, 0);
+        for (int kk = 0; kk < TK; ++kk) {
+          float a[T::FM], bo_re[T::FN], bo_im[T::FN];
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm) a[fm] = As[kk][half][wm * T::BMW + fm * 32 + i];
+#pragma unroll
+          for (int fn = 0; fn < T::FN; ++fn) {
+            const float bre = Bs[kk][0][wn * T::BNW + fn * 32 + i];
+            const float bim = Bs[kk][1][wn * T::BNW + fn * 32 + i];
+            bo_re[fn] = half ? -bim : bre;
+            bo_im[fn] = half ? bre : bim;
+          }
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < T::FN; ++fn) {
+              acc_re[fm][fn] =
+                  __builtin_amdgcn_mfma_f32_32x32x2f32(a[fm], bo_re[fn], acc_re[fm][fn], 0, 0, 0);
+              acc_im[fm][fn] =
+                  __builtin_amdgcn_mfma_f32_32x32x2f32(a[fm], bo_im[fn], acc_im[fm][fn], 0, 0, 0);
+            }
+        }
+      } else if constexpr (PREC == 0) {
+        // 16x16x4: lane l holds k = l / 16 of the instruction's K = 4, i.e.
+        // complex k (l / 32) of the pair and its part (l / 16) % 2.
+        const int i = lane & 15;
+        const int q = lane >> 4;
+        const int kq = q >> 1, part = q & 1;
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 2) {
+          float a[T::FM], bo_re[T::FN], bo_im[T::FN];
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm)
+            a[fm] = As[kk + kq][part][wm * T::BMW + fm * 16 + i];
+#pragma unroll
+          for (int fn = 0; fn < T::FN; ++fn) {
+            const float bre = Bs[kk + kq][0][wn * T::BNW + fn * 16 + i];
+            const float bim = Bs[kk + kq][1][wn * T::BNW + fn * 16 + i];
+            bo_re[fn] = part ? -bim : bre;
+            bo_im[fn] = part ? bre : bim;
+          }
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < T::FN; ++fn) {
+              acc_re[fm][fn] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], bo_re[fn], acc_re[fm][fn], 0, 0, 0);
+              acc_im[fm][fn] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], bo_im[fn], acc_im[fm][fn], 0, 0, 0);
+            }
+        }
+      } else {
+        // Split: lane l supplies 8 consecutive realified k (4 complex) of its
+        // row / column; 32x32x16 takes lanes (row l % 32, k group l / 32) and
+        // 16x16x32 takes (row l % 16, k group l / 16).
+        constexpr int GROUPS = MF == 32 ? 2 : 4;        // k groups of 8 halves per MFMA
+        constexpr int STEPS = (2 * TK) / (8 * GROUPS);  // MFMAs along one slab
+        const int i = MF == 32 ? (lane & 31) : (lane & 15);
+        const int grp = MF == 32 ? (lane >> 5) : (lane >> 4);
+#pragma unroll
+        for (int st = 0; st < STEPS; ++st) {
+          const int ko = st * 8 * GROUPS + 8 * grp;
+          u32x4 ah[T::FM], al[T::FM];
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm) {
+            const int row = wm * T::BMW + fm * MF + i;
+            ah[fm] = *reinterpret_cast<const u32x4*>(Ahi + row * KH + ko);
+            al[fm] = *reinterpret_cast<const u32x4*>(Alo + row * KH + ko);
+          }
+#pragma unroll
+          for (int fn = 0; fn < T::FN; ++fn) {
+            const int col = wn * T::BNW + fn * MF + i;
+            const u32x4 bh = *reinterpret_cast<const u32x4*>(Bhi + col * KH + ko);
+            const u32x4 bl = *reinterpret_cast<const u32x4*>(Blo + col * KH + ko);
+            const u32x4 b1h = conj_im(bh), b1l = conj_im(bl);
+            const u32x4 b2h = swap_pair(bh), b2l = swap_pair(bl);
+#pragma unroll
+            for (int fm = 0; fm < T::FM; ++fm) {
+              if constexpr (MF == 32 && PREC == 1) {
+#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0)
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
+                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
+                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
+#undef XEB_MMA
+              } else if constexpr (MF == 32) {
+#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0)
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
+                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
+                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
+#undef XEB_MMA
+              } else if constexpr (PREC == 1) {
+#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0)
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
+                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
+                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
+#undef XEB_MMA
+              } else {
+#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0)
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
+                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
+                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
+                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
+                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
+#undef XEB_MMA
+              }
+            }
+          }
+        }
       }
       __syncthreads();
     }
 
-    // Park the tile: lane l, register v of the MFMA result hold row
-    // (v % 4) + 4 (l / 32) + 8 (v / 4), column l % 32 of the wave's block.
+    // Park the tile.  32x32 results: lane l, register v hold row (v % 4) +
+    // 4 (l / 32) + 8 (v / 4), column l % 32.  16x16: row 4 (l / 16) + v,
+    // column l % 16.
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int r = wm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
-      const int c = wn * 32 + (lane & 31);
-      Ct[r * (BN + 1) + c] = make_float2(acc_re[v], acc_im[v]);
-    }
+    for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < T::REGS; ++v) {
+          int r, c;
+          if constexpr (MF == 32) {
+            r = wm * T::BMW + fm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+            c = wn * T::BNW + fn * 32 + (lane & 31);
+          } else {
+            r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
+            c = wn * T::BNW + fn * 16 + (lane & 15);
+          }
+          Ct[r * (BN + 1) + c] = make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
+        }
     __syncthreads();
     const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.posM, g.mb) : 0;
     const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.posN, g.nb) : 0;
@@ -223,10 +506,14 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
       int64_t a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
       if (g.pair_mode == 1) a = g.pairs[a];
       if (a < 0) continue;
-      g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = Ct[r * (BN + 1) + c];
+      const float2 val = Ct[r * (BN + 1) + c];
+      g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = val;
+      amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
     }
     __syncthreads();
+    p = pn;
   }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,11 +532,12 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = t;
 }
 
-__global__ void k_accumulate(const float2* partial, const int32_t* rho, double2* amps,
-                             double2* comp, int64_t k) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const float2 p = partial[rho[i]];
+__global__ void k_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
+                             double2* amps, double2* comp, int64_t n) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = idx[j];
+  const float2 p = partial[rho[j]];
   double2 s = amps[i], c = comp[i];
   neumaier(s.x, c.x, double(p.x));
   neumaier(s.y, c.y, double(p.y));
@@ -320,22 +608,76 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   k_contract_generic<<<grid_for(total, 256), 256, 0, s>>>(a);
 }
 
+namespace {
+
+template <int CFG, int PREC>
+unsigned persistent_grid(int64_t tiles) {
+  // Resident workgroups per device for this kernel, queried once per device.
+  static int cached[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int& slot = cached[dev & 63];
+  if (slot == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC>, 256, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    slot = cus * per_cu;
+  }
+  // The walk covers ceil(tiles / 8) * 8 positions; a multiple of 8 keeps each
+  // workgroup on one XCD's share.
+  const int64_t walk = ((tiles + 7) / 8) * 8;
+  const int64_t g = walk < slot ? walk : slot;
+  return unsigned(g < 1 ? 1 : g);
+}
+
+template <int CFG, int PREC>
+void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
+  using T = TileInfo<CFG, PREC>;
+  const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
+  k_contract_mfma<CFG, PREC><<<persistent_grid<CFG, PREC>(tiles), 256, 0, s>>>(a);
+}
+
+template <int PREC>
+void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
+  if (a.tile == 0)
+    launch_cfg<0, PREC>(a, s, rowsA, rowsB);
+  else if (a.tile == 1)
+    launch_cfg<1, PREC>(a, s, rowsA, rowsB);
+  else
+    launch_cfg<2, PREC>(a, s, rowsA, rowsB);
+}
+
+}  // namespace
+
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   const int64_t rowsA = a.nvarA << a.mb;
   const int64_t rowsB = a.nvarB << a.nb;
   if (rowsA <= 0 || rowsB <= 0) return;
-  const int bm = a.tile == 0 ? 64 : 32, bn = a.tile == 0 ? 64 : 128;
-  const int64_t tiles = ((rowsB + bn - 1) / bn) * ((rowsA + bm - 1) / bm);
-  const unsigned grid = unsigned(tiles < (int64_t(1) << 22) ? tiles : (int64_t(1) << 22));
-  if (a.tile == 0)
-    k_contract_mfma<64, 64><<<grid, 256, 0, s>>>(a);
+  if (a.prec == 0)
+    launch_prec<0>(a, s, rowsA, rowsB);
+  else if (a.prec == 1)
+    launch_prec<1>(a, s, rowsA, rowsB);
   else
-    k_contract_mfma<32, 128><<<grid, 256, 0, s>>>(a);
+    launch_prec<2>(a, s, rowsA, rowsB);
+}
+
+void prepare_mfma_launch(int prec) {
+  if (prec == 0) {
+    (void)persistent_grid<0, 0>(1), (void)persistent_grid<1, 0>(1), (void)persistent_grid<2, 0>(1);
+  } else if (prec == 1) {
+    (void)persistent_grid<0, 1>(1), (void)persistent_grid<1, 1>(1), (void)persistent_grid<2, 1>(1);
+  } else {
+    (void)persistent_grid<0, 2>(1), (void)persistent_grid<1, 2>(1), (void)persistent_grid<2, 2>(1);
+  }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  *bm = tile == 0 ? 64 : 32;
-  *bn = tile == 0 ? 64 : 128;
+  *bm = tile == 0 ? 64 : (tile == 1 ? 32 : 16);
+  *bn = tile == 0 ? 64 : (tile == 1 ? 128 : 256);
 }
 
 void launch_zero(void* p, uint64_t bytes, hipStream_t s) {
@@ -344,10 +686,10 @@ void launch_zero(void* p, uint64_t bytes, hipStream_t s) {
   k_zero<<<grid_for(int64_t(words), 256), 256, 0, s>>>(static_cast<uint32_t*>(p), words);
 }
 
-void launch_accumulate(const float2* partial, const int32_t* rho, double2* amps, double2* comp,
-                       int64_t k, hipStream_t s) {
-  if (k <= 0) return;
-  k_accumulate<<<grid_for(k, 256), 256, 0, s>>>(partial, rho, amps, comp, k);
+void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
+                       double2* amps, double2* comp, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_accumulate<<<grid_for(n, 256), 256, 0, s>>>(partial, idx, rho, amps, comp, n);
 }
 
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s) {

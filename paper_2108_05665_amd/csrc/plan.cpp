@@ -4,22 +4,23 @@
 //  * network of the circuit; output legs and sliced legs are projected into
 //    the leaves that carry them, which become variables whose values are the
 //    projected tensors (section "Multi-batch simulator"; Appendix A, "Slicing");
-//  * the strings are deduplicated; every node gets the distinct keys of its
-//    subtree in lexicographic order of (left key, right key), i.e. the order of
-//    Appendix C with variables ordered as they occur in the tree, and gather
-//    maps to its children's keys.  |keys| is the exact evaluation count |t_T|;
+//  * the distinct strings are sorted in the lexicographic order of their
+//    tuples, variables ordered as they occur in the tree (Appendix C), and cut
+//    into contiguous blocks; within a block every node gets its distinct keys
+//    in lexicographic order of (left key, right key) and gather maps to its
+//    children's keys.  |keys| is the exact evaluation count |t_T|;
 //  * a top-down pass fixes every tensor's leg order so that the legs a node
 //    shares with its sibling are the low (contiguous) bits and each parent's
 //    kernel writes its result directly in the order its own parent reads;
-//  * a dry run of the schedule sizes the device workspace (Appendix C,
-//    "emulation mode").
+//  * a dry run sizes the device workspace (Appendix C, "emulation mode") and
+//    picks the smallest number of string blocks whose tables fit the budget.
 //
-// Execution (xeb_contract): slices in increasing order; within one call a
-// node is contracted again only when the slice bits it depends on change (its
-// table of all string keys stays resident otherwise), which is the single
-// cached entry per subtree of the paper's K_L cache applied to slice
-// variables; the root's partial amplitudes are added into FP64 with
-// compensation.
+// Execution (xeb_contract): block by block, slices in increasing order; within
+// a block a node is contracted again only when the slice bits it depends on
+// change (its table of all the block's keys stays resident otherwise), the
+// single cached entry per subtree of the paper's K_L cache applied to slice
+// variables; a node that sees no output leg keeps its table across blocks.
+// The root's partial amplitudes are added into FP64 with compensation.
 
 #include "plan.h"
 
@@ -38,6 +39,8 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+// Index arrays (gather maps, string maps) only need 16-byte alignment.
+uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 
 struct DeviceGuard {
   int prev = -1;
@@ -66,6 +69,54 @@ double evals_over_all_slices(uint64_t smask, int s) {
   return std::ldexp(1.0, s - __builtin_ctzll(smask));
 }
 
+void leaves_dfs(const std::vector<Node>& nodes, int t, std::vector<int>& out) {
+  if (nodes[t].leaf) {
+    out.push_back(t);
+    return;
+  }
+  leaves_dfs(nodes, nodes[t].left, out);
+  leaves_dfs(nodes, nodes[t].right, out);
+}
+
+// Kernel choice for one node's keys in one block.  MFMA when the stacked GEMM
+// is big enough and its padded tile work stays within 8x the useful MACs; the
+// smaller side supplies the tile rows.
+void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, bool force_generic) {
+  const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
+  const double rowsL = double(nvarL) * std::ldexp(1.0, nd.mb);
+  const double rowsR = double(nvarR) * std::ldexp(1.0, nd.nb);
+  const double pairs = double(nvarL) * double(nvarR);
+  nb.swapped = (rowsR < rowsL && rowsR < 64) ? 1 : 0;
+  const double rows = nb.swapped ? rowsR : rowsL;
+  const double cols = nb.swapped ? rowsL : rowsR;
+  nb.tile = rows <= 16 ? 2 : (rows <= 32 ? 1 : 0);
+  int bm = 0, bn = 0;
+  mfma_tile_shape(nb.tile, &bm, &bn);
+  const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
+                      std::max(std::ldexp(1.0, nd.kb), double(16));
+  nb.kernel = XEB_KERNEL_GENERIC;
+  if (force_generic || nd.kb < 1 || rows < 4 || cols < 64 || useful < 65536.0 ||
+      8 * useful < work || pairs > double(1 << 26))
+    return;
+  nb.kernel = XEB_KERNEL_MFMA;
+  // Epilogue write order: tile bits sorted by the output position they feed;
+  // bits that select keys come last (columns before rows).
+  const int kmb = nb.swapped ? nd.nb : nd.mb, knb = nb.swapped ? nd.mb : nd.nb;
+  const int8_t* kpm = nb.swapped ? nd.posN : nd.posM;
+  const int8_t* kpn = nb.swapped ? nd.posM : nd.posN;
+  std::vector<std::pair<int, int>> keyed;  // (key, code)
+  for (int j = 0; (1 << j) < bm; ++j) keyed.push_back({j < kmb ? int(kpm[j]) : 2000 + j, j});
+  for (int j = 0; (1 << j) < bn; ++j) keyed.push_back({j < knb ? int(kpn[j]) : 1000 + j, 32 + j});
+  std::sort(keyed.begin(), keyed.end());
+  for (size_t b = 0; b < keyed.size(); ++b) nb.ubit[b] = int8_t(keyed[b].second);
+  nb.pair_mode = (nb.nvar == nvarL * nvarR) ? 0 : 1;
+  if (nb.pair_mode == 1) {
+    nb.pairs.assign(size_t(nvarL * nvarR), -1);
+    for (int64_t v = 0; v < nb.nvar; ++v)
+      nb.pairs[size_t(int64_t(nb.lidx[v]) * nvarR + nb.ridx[v])] = int32_t(v);
+  }
+}
+
 }  // namespace
 
 void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t k,
@@ -74,7 +125,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   xeb_options_t o;
   xeb_options_default(&o);
   if (opt) o = *opt;
-  if (o.precision != XEB_PREC_C64) fail(XEB_EINVAL, "only XEB_PREC_C64 is available");
+  if (o.precision != XEB_PREC_C64 && o.precision != XEB_PREC_SPLIT_FP16 &&
+      o.precision != XEB_PREC_SPLIT_BF16)
+    fail(XEB_EINVAL, "unknown precision");
   if (o.device < 0) fail(XEB_EINVAL, "device ordinal is negative");
   p.opt = o;
 
@@ -156,56 +209,6 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   }
   if (!p.nodes[p.root].legs.empty()) fail(XEB_EINVAL, "the tree does not close the network");
 
-  // ---- string keys per node (Appendix C: tuples, lexicographic order) ------
-  std::vector<uint64_t> ds(bits, bits + k);
-  std::sort(ds.begin(), ds.end());
-  ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
-  const int64_t kd = int64_t(ds.size());
-  p.k = k;
-  p.kd = kd;
-  std::vector<std::vector<int32_t>> var(nn);
-  for (int j = 0; j < L; ++j) {
-    Node& nd = p.nodes[j];
-    std::vector<uint64_t> keys(kd);
-    for (int64_t i = 0; i < kd; ++i) keys[i] = pext64(ds[i], nd.outmask);
-    std::vector<uint64_t> uk(keys);
-    std::sort(uk.begin(), uk.end());
-    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
-    if (uk.empty()) uk.push_back(0);
-    nd.leaf_keys = uk;
-    nd.nvar = int64_t(uk.size());
-    var[j].resize(kd);
-    for (int64_t i = 0; i < kd; ++i)
-      var[j][i] = int32_t(std::lower_bound(uk.begin(), uk.end(), keys[i]) - uk.begin());
-  }
-  for (int T = L; T < nn; ++T) {
-    Node& nd = p.nodes[T];
-    const int64_t nb_var = p.nodes[nd.right].nvar;
-    std::vector<int64_t> codes(kd);
-    for (int64_t i = 0; i < kd; ++i) codes[i] = int64_t(var[nd.left][i]) * nb_var + var[nd.right][i];
-    std::vector<int64_t> uc(codes);
-    std::sort(uc.begin(), uc.end());
-    uc.erase(std::unique(uc.begin(), uc.end()), uc.end());
-    if (uc.empty()) uc.push_back(0);
-    nd.nvar = int64_t(uc.size());
-    nd.lidx.resize(nd.nvar);
-    nd.ridx.resize(nd.nvar);
-    for (int64_t v = 0; v < nd.nvar; ++v) {
-      nd.lidx[v] = int32_t(uc[v] / nb_var);
-      nd.ridx[v] = int32_t(uc[v] % nb_var);
-    }
-    var[T].resize(kd);
-    for (int64_t i = 0; i < kd; ++i)
-      var[T][i] = int32_t(std::lower_bound(uc.begin(), uc.end(), codes[i]) - uc.begin());
-    std::vector<int32_t>().swap(var[nd.left]);
-    std::vector<int32_t>().swap(var[nd.right]);
-  }
-  p.rho.resize(k);
-  for (int64_t i = 0; i < k; ++i) {
-    const int64_t d = std::lower_bound(ds.begin(), ds.end(), bits[i]) - ds.begin();
-    p.rho[i] = var[p.root][d];
-  }
-
   // ---- layouts (top-down) -------------------------------------------------
   std::vector<int> pos(net.n_legs, -1);
   for (int T = nn - 1; T >= L; --T) {
@@ -232,91 +235,182 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     b.legs.insert(b.legs.end(), N.begin(), N.end());
   }
 
-  // ---- kernel per node ------------------------------------------------------
-  // MFMA when the stacked GEMM is big enough and its padded tile work stays
-  // within 8x the useful MACs; the smaller side supplies the tile rows.
-  for (int T = L; T < nn; ++T) {
-    Node& nd = p.nodes[T];
-    const Node& a = p.nodes[nd.left];
-    const Node& b = p.nodes[nd.right];
-    const double useful = double(nd.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
-    const double rowsL = double(a.nvar) * std::ldexp(1.0, nd.mb);
-    const double rowsR = double(b.nvar) * std::ldexp(1.0, nd.nb);
-    const double pairs = double(a.nvar) * double(b.nvar);
-    nd.swapped = (rowsR < rowsL && rowsR < 64) ? 1 : 0;
-    const double rows = nd.swapped ? rowsR : rowsL;
-    const double cols = nd.swapped ? rowsL : rowsR;
-    nd.tile = rows <= 32 ? 1 : 0;
-    int bm = 0, bn = 0;
-    mfma_tile_shape(nd.tile, &bm, &bn);
-    const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
-                        std::max(std::ldexp(1.0, nd.kb), double(16));
-    nd.kernel = XEB_KERNEL_GENERIC;
-    if (!o.force_generic && nd.kb >= 1 && rows >= 8 && cols >= 32 && useful >= 65536.0 &&
-        8 * useful >= work && pairs <= double(1 << 26)) {
-      nd.kernel = XEB_KERNEL_MFMA;
-      // Epilogue write order: tile bits sorted by the output position they
-      // feed; bits that select variants come last (columns before rows).
-      const int kmb = nd.swapped ? nd.nb : nd.mb, knb = nd.swapped ? nd.mb : nd.nb;
-      const int8_t* kpm = nd.swapped ? nd.posN : nd.posM;
-      const int8_t* kpn = nd.swapped ? nd.posM : nd.posN;
-      std::vector<std::pair<int, int>> keyed;  // (key, code)
-      for (int j = 0; (1 << j) < bm; ++j) keyed.push_back({j < kmb ? int(kpm[j]) : 2000 + j, j});
-      for (int j = 0; (1 << j) < bn; ++j)
-        keyed.push_back({j < knb ? int(kpn[j]) : 1000 + j, 32 + j});
-      std::sort(keyed.begin(), keyed.end());
-      for (size_t b2 = 0; b2 < keyed.size(); ++b2) nd.ubit[b2] = int8_t(keyed[b2].second);
-      nd.pair_mode = (nd.nvar == a.nvar * b.nvar) ? 0 : 1;
-      if (nd.pair_mode == 1) {
-        nd.pairs.assign(size_t(a.nvar * b.nvar), -1);
-        for (int64_t v = 0; v < nd.nvar; ++v)
-          nd.pairs[size_t(int64_t(nd.lidx[v]) * b.nvar + nd.ridx[v])] = int32_t(v);
+  // ---- strings in lexicographic tuple order (Appendix C) --------------------
+  // A string's tuple lists its leaf keys in depth-first leaf order; with every
+  // output qubit on exactly one leaf the concatenated keys fit in 64 bits.
+  std::vector<uint64_t> ds(bits, bits + k);
+  std::sort(ds.begin(), ds.end());
+  ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+  const int64_t kd = int64_t(ds.size());
+  p.k = k;
+  p.kd = kd;
+  std::vector<int> dfs;
+  leaves_dfs(p.nodes, p.root, dfs);
+  {
+    std::vector<std::pair<uint64_t, uint64_t>> keyed(kd);
+    for (int64_t i = 0; i < kd; ++i) {
+      uint64_t key = 0;
+      for (int j : dfs) {
+        const uint64_t om = p.nodes[j].outmask;
+        if (!om) continue;
+        const int w = popcount64(om);
+        key = (w == 64 ? 0 : (key << w)) | pext64(ds[i], om);
       }
+      keyed[i] = {key, ds[i]};
     }
+    std::sort(keyed.begin(), keyed.end());
+    for (int64_t i = 0; i < kd; ++i) ds[i] = keyed[i].second;
   }
 
-  // ---- workspace (dry run) --------------------------------------------------
-  // Static region (uploaded at bind): leaf tables, gather maps, rho.
-  uint64_t off = 0;
+  // ---- leaf keys (over all strings) -----------------------------------------
+  std::vector<std::vector<int32_t>> leaf_var(L);
   for (int j = 0; j < L; ++j) {
     Node& nd = p.nodes[j];
-    nd.off_table = off;
-    off += align_up(uint64_t(nd.nslicekeys) * nd.nvar * nd.size() * 8);
+    std::vector<uint64_t> keys(kd);
+    for (int64_t i = 0; i < kd; ++i) keys[i] = pext64(ds[i], nd.outmask);
+    std::vector<uint64_t> uk(keys);
+    std::sort(uk.begin(), uk.end());
+    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+    if (uk.empty()) uk.push_back(0);
+    nd.leaf_keys = uk;
+    nd.leaf_nvar = int64_t(uk.size());
+    leaf_var[j].resize(kd);
+    for (int64_t i = 0; i < kd; ++i)
+      leaf_var[j][i] = int32_t(std::lower_bound(uk.begin(), uk.end(), keys[i]) - uk.begin());
   }
-  p.leaf_bytes = off;
-  for (int T = L; T < nn; ++T) {
-    Node& nd = p.nodes[T];
-    if (nd.kernel == XEB_KERNEL_GENERIC) {
-      nd.off_lidx = off;
-      off += align_up(uint64_t(nd.nvar) * 4);
-      nd.off_ridx = off;
-      off += align_up(uint64_t(nd.nvar) * 4);
-    } else if (nd.pair_mode == 1) {
-      nd.off_pairs = off;
-      off += align_up(nd.pairs.size() * 4);
+  // Position of every input string among the sorted distinct strings.
+  std::vector<int64_t> where(k);
+  {
+    std::vector<std::pair<uint64_t, int64_t>> sorted_pos(kd);
+    for (int64_t i = 0; i < kd; ++i) sorted_pos[i] = {ds[i], i};
+    std::sort(sorted_pos.begin(), sorted_pos.end());
+    for (int64_t i = 0; i < k; ++i) {
+      auto it = std::lower_bound(sorted_pos.begin(), sorted_pos.end(),
+                                 std::make_pair(bits[i], int64_t(-1)));
+      where[i] = it->second;
     }
   }
-  p.off_rho = off;
-  off += align_up(uint64_t(k) * 4);
-  const uint64_t static_bytes = off;
-  // Dynamic region: node tables, compensation, scratch.
-  for (int T = L; T < nn; ++T) {
-    Node& nd = p.nodes[T];
-    nd.off_table = off;
-    off += align_up(uint64_t(nd.nvar) * nd.size() * 8);
+
+  // Keys of every internal node among the strings [first, first + count).
+  auto build_block = [&](int64_t first, int64_t count) {
+    Block blk;
+    blk.first = first;
+    blk.count = count;
+    blk.nodes.resize(nn - L);
+    std::vector<std::vector<int32_t>> var(nn);
+    auto var_of = [&](int id, int64_t i) -> int32_t {
+      return p.nodes[id].leaf ? leaf_var[id][first + i] : var[id][i];
+    };
+    auto nvar_of = [&](int id) -> int64_t {
+      return p.nodes[id].leaf ? p.nodes[id].leaf_nvar : blk.nodes[id - L].nvar;
+    };
+    for (int T = L; T < nn; ++T) {
+      const Node& nd = p.nodes[T];
+      NodeBlock& nb = blk.nodes[T - L];
+      const int64_t nr = nvar_of(nd.right);
+      std::vector<int64_t> codes(count);
+      for (int64_t i = 0; i < count; ++i)
+        codes[i] = int64_t(var_of(nd.left, i)) * nr + var_of(nd.right, i);
+      std::vector<int64_t> uc(codes);
+      std::sort(uc.begin(), uc.end());
+      uc.erase(std::unique(uc.begin(), uc.end()), uc.end());
+      if (uc.empty()) uc.push_back(0);
+      nb.nvar = int64_t(uc.size());
+      nb.lidx.resize(nb.nvar);
+      nb.ridx.resize(nb.nvar);
+      for (int64_t v = 0; v < nb.nvar; ++v) {
+        nb.lidx[v] = int32_t(uc[v] / nr);
+        nb.ridx[v] = int32_t(uc[v] % nr);
+      }
+      var[T].resize(count);
+      for (int64_t i = 0; i < count; ++i)
+        var[T][i] = int32_t(std::lower_bound(uc.begin(), uc.end(), codes[i]) - uc.begin());
+      if (!p.nodes[nd.left].leaf) std::vector<int32_t>().swap(var[nd.left]);
+      if (!p.nodes[nd.right].leaf) std::vector<int32_t>().swap(var[nd.right]);
+      choose_kernel(nd, nvar_of(nd.left), nr, nb, o.force_generic != 0);
+    }
+    for (int64_t i = 0; i < k; ++i) {
+      const int64_t d = where[i];
+      if (d < first || d >= first + count) continue;
+      blk.idx.push_back(int32_t(i));
+      blk.rho.push_back(L == 1 ? leaf_var[0][d] : var[p.root][d - first]);
+    }
+    return blk;
+  };
+
+  // ---- workspace (dry run) --------------------------------------------------
+  // Static region (uploaded at bind): leaf tables, per-block gather maps and
+  // string maps, leaf amax.  Dynamic region: node tables (sized for the
+  // largest block), amax slots, compensation, scratch.
+  auto layout = [&](std::vector<Block>& blocks) -> uint64_t {
+    uint64_t off = 0;
+    for (int j = 0; j < L; ++j) {
+      Node& nd = p.nodes[j];
+      nd.off_table = off;
+      off += align_up(uint64_t(nd.nslicekeys) * nd.leaf_nvar * nd.size() * 8);
+    }
+    for (Block& blk : blocks) {
+      for (NodeBlock& nb : blk.nodes) {
+        if (nb.kernel == XEB_KERNEL_GENERIC) {
+          nb.off_lidx = off;
+          off += align16(uint64_t(nb.nvar) * 4);
+          nb.off_ridx = off;
+          off += align16(uint64_t(nb.nvar) * 4);
+        } else if (nb.pair_mode == 1) {
+          nb.off_pairs = off;
+          off += align16(nb.pairs.size() * 4);
+        }
+      }
+      blk.off_idx = off;
+      off += align16(blk.idx.size() * 4);
+      blk.off_rho = off;
+      off += align16(blk.rho.size() * 4);
+    }
+    p.off_leaf_amax = off;
+    off += align_up(uint64_t(nn) * 4);
+    const uint64_t static_end = off;
+    for (int T = L; T < nn; ++T) {
+      Node& nd = p.nodes[T];
+      nd.table_nvar = 1;
+      for (const Block& blk : blocks) nd.table_nvar = std::max(nd.table_nvar, blk.nodes[T - L].nvar);
+      nd.off_table = off;
+      off += align_up(uint64_t(nd.table_nvar) * nd.size() * 8);
+    }
+    p.off_amax = off;
+    off += align_up(uint64_t(nn) * 8);
+    p.off_comp = off;
+    off += align_up(uint64_t(k) * 16);
+    p.off_scratch = off;
+    off += kAlign;
+    p.ws_bytes = off;
+    return static_end;
+  };
+
+  // Smallest power-of-two block count that fits; stop when more blocks no
+  // longer shrink the workspace.
+  uint64_t static_bytes = 0;
+  uint64_t prev_bytes = ~uint64_t(0);
+  for (int64_t nblocks = 1;; nblocks *= 2) {
+    if (kd > 0 && nblocks > kd) nblocks = kd;
+    std::vector<Block> blocks;
+    const int64_t nbk = std::max<int64_t>(nblocks, 1);
+    for (int64_t b = 0; b < nbk; ++b) {
+      const int64_t first = kd * b / nbk, last = kd * (b + 1) / nbk;
+      if (last > first || kd == 0) blocks.push_back(build_block(first, last - first));
+    }
+    static_bytes = layout(blocks);
+    p.blocks = std::move(blocks);
+    if (!o.memory_budget || p.ws_bytes <= o.memory_budget) break;
+    if (nblocks >= std::max<int64_t>(kd, 1) || p.ws_bytes >= prev_bytes)
+      fail(XEB_ENOMEM, "workspace of " + std::to_string(p.ws_bytes) +
+                           " bytes exceeds the budget; more string blocks do not shrink it");
+    prev_bytes = p.ws_bytes;
   }
-  p.off_comp = off;
-  off += align_up(uint64_t(k) * 16);
-  p.off_scratch = off;
-  off += kAlign;
-  p.ws_bytes = off;
-  if (o.memory_budget && p.ws_bytes > o.memory_budget)
-    fail(XEB_ENOMEM, "workspace of " + std::to_string(p.ws_bytes) + " bytes exceeds the budget");
 
   // ---- leaf tables (FP64 -> complex64) --------------------------------------
-  p.leaf_staging.assign(static_bytes / 4, 0.f);
+  p.staging.assign(static_bytes / 4, 0.f);
   for (int j = 0; j < L; ++j) {
-    const Node& nd = p.nodes[j];
+    Node& nd = p.nodes[j];
     const NetLeaf& nl = net.leaves[j];
     const int R = int(nl.legs.size());
     const int r = int(nd.legs.size());
@@ -324,9 +418,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     for (int a = 0; a < R; ++a)
       for (int q = 0; q < r; ++q)
         if (nd.legs[q] == nl.legs[a]) axis_pos[a] = q;
-    float* dst = p.leaf_staging.data() + nd.off_table / 4;
+    float* dst = p.staging.data() + nd.off_table / 4;
     for (int64_t kappa = 0; kappa < nd.nslicekeys; ++kappa)
-      for (int64_t v = 0; v < nd.nvar; ++v)
+      for (int64_t v = 0; v < nd.leaf_nvar; ++v)
         for (int64_t e = 0; e < nd.size(); ++e) {
           int64_t idx = 0;
           for (int a = 0; a < R; ++a) {
@@ -341,21 +435,29 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
             idx |= int64_t(bit) << (R - 1 - a);
           }
           const cplx x = nl.data[idx];
-          const int64_t o2 = ((kappa * nd.nvar + v) * nd.size() + e) * 2;
+          const int64_t o2 = ((kappa * nd.leaf_nvar + v) * nd.size() + e) * 2;
           dst[o2] = float(x.real());
           dst[o2 + 1] = float(x.imag());
+          nd.leaf_amax = std::max(nd.leaf_amax, std::max(std::fabs(dst[o2]), std::fabs(dst[o2 + 1])));
         }
+    // Largest magnitude of the leaf table (the FP16 scale of a leaf operand).
+    std::memcpy(p.staging.data() + p.off_leaf_amax / 4 + j, &nd.leaf_amax, 4);
   }
-  for (int T = L; T < nn; ++T) {
-    const Node& nd = p.nodes[T];
-    if (nd.kernel == XEB_KERNEL_GENERIC) {
-      std::memcpy(p.leaf_staging.data() + nd.off_lidx / 4, nd.lidx.data(), nd.lidx.size() * 4);
-      std::memcpy(p.leaf_staging.data() + nd.off_ridx / 4, nd.ridx.data(), nd.ridx.size() * 4);
-    } else if (nd.pair_mode == 1) {
-      std::memcpy(p.leaf_staging.data() + nd.off_pairs / 4, nd.pairs.data(), nd.pairs.size() * 4);
+  auto put = [&](uint64_t off, const std::vector<int32_t>& v) {
+    if (!v.empty()) std::memcpy(p.staging.data() + off / 4, v.data(), v.size() * 4);
+  };
+  for (Block& blk : p.blocks) {
+    for (NodeBlock& nb : blk.nodes) {
+      if (nb.kernel == XEB_KERNEL_GENERIC) {
+        put(nb.off_lidx, nb.lidx);
+        put(nb.off_ridx, nb.ridx);
+      } else if (nb.pair_mode == 1) {
+        put(nb.off_pairs, nb.pairs);
+      }
     }
+    put(blk.off_idx, blk.idx);
+    put(blk.off_rho, blk.rho);
   }
-  if (k > 0) std::memcpy(p.leaf_staging.data() + p.off_rho / 4, p.rho.data(), size_t(k) * 4);
 
   // ---- stats -----------------------------------------------------------------
   xeb_stats_t& st = p.stats;
@@ -366,31 +468,42 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   st.k_distinct = kd;
   st.n_qubits = n;
   st.n_sliced = s;
-  for (int T = 0; T < nn; ++T) {
-    const Node& nd = p.nodes[T];
-    st.max_tensor_elems = std::max<int64_t>(st.max_tensor_elems, nd.size());
-    if (nd.leaf) continue;
-    const Node& a = p.nodes[nd.left];
-    const Node& b = p.nodes[nd.right];
-    st.sum_variants += nd.nvar;
-    const double cm = double(nd.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
-    const double ev = evals_over_all_slices(nd.smask, s);
-    st.cmacs_per_slice += cm;
-    st.cmacs_full += ev * cm;
-    st.rw_elems_full += ev * (double(a.nvar) * a.size() + double(b.nvar) * b.size() +
-                              double(nd.nvar) * nd.size());
-    st.evals_full += ev;
+  st.n_blocks = int64_t(p.blocks.size());
+  for (int T = 0; T < nn; ++T)
+    st.max_tensor_elems = std::max<int64_t>(st.max_tensor_elems, p.nodes[T].size());
+  for (const Block& blk : p.blocks) {
+    auto nv = [&](int id) {
+      return p.nodes[id].leaf ? p.nodes[id].leaf_nvar : blk.nodes[id - L].nvar;
+    };
+    for (int T = L; T < nn; ++T) {
+      const Node& nd = p.nodes[T];
+      const NodeBlock& nb = blk.nodes[T - L];
+      st.sum_variants += nb.nvar;
+      const double cm = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
+      // A node without output legs keeps its table across blocks when it
+      // depends on no slice bit.
+      const bool kept = nd.outmask == 0 && nd.smask == 0 && &blk != &p.blocks.front();
+      const double ev = kept ? 0.0 : evals_over_all_slices(nd.smask, s);
+      st.cmacs_per_slice += cm;
+      st.cmacs_full += ev * cm;
+      st.rw_elems_full += ev * (double(nv(nd.left)) * p.nodes[nd.left].size() +
+                                double(nv(nd.right)) * p.nodes[nd.right].size() +
+                                double(nb.nvar) * nd.size());
+      st.evals_full += ev;
+    }
   }
   st.workspace_bytes = p.ws_bytes;
 
   if (o.trace > 0) {
+    const Block& blk = p.blocks.front();
     for (int T = L; T < nn; ++T) {
       const Node& nd = p.nodes[T];
+      const NodeBlock& nb = blk.nodes[T - L];
       std::fprintf(stderr,
                    "{\"node\":%d,\"left\":%d,\"right\":%d,\"variants\":%lld,\"m_bits\":%d,"
-                   "\"n_bits\":%d,\"k_bits\":%d,\"slice_mask\":%llu,\"kernel\":%d}\n",
-                   T, nd.left, nd.right, (long long)nd.nvar, nd.mb, nd.nb, nd.kb,
-                   (unsigned long long)nd.smask, nd.kernel);
+                   "\"n_bits\":%d,\"k_bits\":%d,\"slice_mask\":%llu,\"kernel\":%d,\"blocks\":%zu}\n",
+                   T, nd.left, nd.right, (long long)nb.nvar, nd.mb, nd.nb, nd.kb,
+                   (unsigned long long)nd.smask, nb.kernel, p.blocks.size());
     }
   }
 }
@@ -402,9 +515,8 @@ void bind_plan(Plan* p, void* dev, uint64_t bytes) {
     fail(XEB_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, plan needs " +
                          std::to_string(p->ws_bytes));
   DeviceGuard g(p->opt.device);
-  if (!p->leaf_staging.empty())
-    hip_check(hipMemcpy(dev, p->leaf_staging.data(), p->leaf_staging.size() * 4,
-                        hipMemcpyHostToDevice),
+  if (!p->staging.empty())
+    hip_check(hipMemcpy(dev, p->staging.data(), p->staging.size() * 4, hipMemcpyHostToDevice),
               "upload of leaf tables");
   p->ws = dev;
   p->ws_size = bytes;
@@ -442,12 +554,13 @@ void recycle_records(Plan* p) {
 
 // Records an event pair around `launch` when profiling is on.
 template <class F>
-void timed(Plan* p, hipStream_t stream, int kernel, double cmacs, double bytes, F&& launch) {
-  if (!p->profiling) {
+void timed(Plan* p, hipStream_t stream, int kernel, int node, double cmacs, double bytes,
+           F&& launch) {
+  if (!p->profiling || p->capturing) {
     launch();
     return;
   }
-  ProfRecord r{take_event(p), take_event(p), kernel, cmacs, bytes};
+  ProfRecord r{take_event(p), take_event(p), kernel, node, cmacs, bytes};
   hip_check(hipEventRecord(r.start, stream), "hipEventRecord");
   launch();
   hip_check(hipEventRecord(r.stop, stream), "hipEventRecord");
@@ -465,11 +578,12 @@ void set_profiling(Plan* p, bool on) {
   p->profiling = on;
 }
 
-xeb_kernel_profile_t read_profile(Plan* p, int kernel) {
+xeb_kernel_profile_t read_profile(Plan* p, int kernel, int node) {
   DeviceGuard g(p->opt.device);
   xeb_kernel_profile_t out{};
   for (ProfRecord& r : p->prof) {
-    if (r.kernel != kernel) continue;
+    if (kernel >= 0 && r.kernel != kernel) continue;
+    if (node >= 0 && r.node != node) continue;
     hip_check(hipEventSynchronize(r.stop), "hipEventSynchronize");
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, r.start, r.stop), "hipEventElapsedTime");
@@ -483,12 +597,14 @@ xeb_kernel_profile_t read_profile(Plan* p, int kernel) {
 
 namespace {
 
+// Current table of a node for slice sigma: internal nodes hold the block's
+// keys; a leaf's sub-table is picked by its slice key.
 const float2* node_ptr(const Plan* p, int id, int64_t sigma) {
   const Node& nd = p->nodes[id];
   const char* base = static_cast<const char*>(p->ws) + nd.off_table;
   if (nd.leaf) {
     const uint64_t kappa = pext64(uint64_t(sigma), nd.smask);
-    base += kappa * uint64_t(nd.nvar) * nd.size() * 8;
+    base += kappa * uint64_t(nd.leaf_nvar) * nd.size() * 8;
   }
   return reinterpret_cast<const float2*>(base);
 }
@@ -504,57 +620,89 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
   DeviceGuard g(p->opt.device);
   char* ws = static_cast<char*>(p->ws);
   double2* comp = reinterpret_cast<double2*>(ws + p->off_comp);
-  const int32_t* rho = reinterpret_cast<const int32_t*>(ws + p->off_rho);
   launch_zero(comp, uint64_t(p->k) * 16, stream);
   // Every call starts from its first slice: no table computed by an earlier
   // call is reused, so a call's cost does not depend on its predecessors.
-  for (Node& nd : p->nodes) nd.valid = false;
-  for (int64_t sigma = b; sigma < e; ++sigma) {
-    for (int T = p->n_leaves; T < int(p->nodes.size()); ++T) {
-      Node& nd = p->nodes[T];
-      const uint64_t key = uint64_t(sigma) & nd.smask;
-      if (nd.valid && nd.cur_key == key) continue;
-      const Node& na = p->nodes[nd.left];
-      const Node& nb = p->nodes[nd.right];
-      ContractArgs a{};
-      const bool sw = nd.kernel == XEB_KERNEL_MFMA && nd.swapped;
-      a.A = node_ptr(p, sw ? nd.right : nd.left, sigma);
-      a.B = node_ptr(p, sw ? nd.left : nd.right, sigma);
-      a.C = reinterpret_cast<float2*>(ws + nd.off_table);
-      a.nvar = nd.nvar;
-      a.nvarA = sw ? nb.nvar : na.nvar;
-      a.nvarB = sw ? na.nvar : nb.nvar;
-      a.mb = sw ? nd.nb : nd.mb;
-      a.nb = sw ? nd.mb : nd.nb;
-      a.kb = nd.kb;
-      a.pair_mode = nd.pair_mode;
-      a.swapped = sw ? 1 : 0;
-      a.tile = nd.tile;
-      std::memcpy(a.posM, sw ? nd.posN : nd.posM, sizeof(a.posM));
-      std::memcpy(a.posN, sw ? nd.posM : nd.posN, sizeof(a.posN));
-      std::memcpy(a.ubit, nd.ubit, sizeof(a.ubit));
-      const double cmacs = double(nd.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
-      const double bytes = 8.0 * (double(na.nvar) * na.size() + double(nb.nvar) * nb.size() +
-                                  double(nd.nvar) * nd.size());
-      if (nd.kernel == XEB_KERNEL_MFMA) {
-        a.pairs = nd.pair_mode == 1 ? reinterpret_cast<const int32_t*>(ws + nd.off_pairs) : nullptr;
-        timed(p, stream, XEB_KERNEL_MFMA, cmacs, bytes, [&] { launch_contract_mfma(a, stream); });
-      } else {
-        a.lidx = reinterpret_cast<const int32_t*>(ws + nd.off_lidx);
-        a.ridx = reinterpret_cast<const int32_t*>(ws + nd.off_ridx);
-        timed(p, stream, XEB_KERNEL_GENERIC, cmacs, bytes,
-              [&] { launch_contract_generic(a, stream); });
+  for (Node& nd : p->nodes) {
+    nd.valid = false;
+    nd.epoch = 0;
+    nd.cur_block = -1;
+  }
+  const bool fp16 = p->opt.precision == XEB_PREC_SPLIT_FP16;
+  if (fp16) launch_zero(ws + p->off_amax, uint64_t(p->nodes.size()) * 8, stream);
+  const int L = p->n_leaves;
+  for (int bi = 0; bi < int(p->blocks.size()); ++bi) {
+    const Block& blk = p->blocks[bi];
+    auto nvar_of = [&](int id) -> int64_t {
+      return p->nodes[id].leaf ? p->nodes[id].leaf_nvar : blk.nodes[id - L].nvar;
+    };
+    for (int64_t sigma = b; sigma < e; ++sigma) {
+      for (int T = L; T < int(p->nodes.size()); ++T) {
+        Node& nd = p->nodes[T];
+        const NodeBlock& nb = blk.nodes[T - L];
+        const uint64_t key = uint64_t(sigma) & nd.smask;
+        if (nd.valid && nd.cur_key == key && (nd.outmask == 0 || nd.cur_block == bi)) continue;
+        const Node& na = p->nodes[nd.left];
+        const Node& nr = p->nodes[nd.right];
+        ContractArgs a{};
+        const bool sw = nb.kernel == XEB_KERNEL_MFMA && nb.swapped;
+        a.A = node_ptr(p, sw ? nd.right : nd.left, sigma);
+        a.B = node_ptr(p, sw ? nd.left : nd.right, sigma);
+        a.C = reinterpret_cast<float2*>(ws + nd.off_table);
+        a.nvar = nb.nvar;
+        a.nvarA = nvar_of(sw ? nd.right : nd.left);
+        a.nvarB = nvar_of(sw ? nd.left : nd.right);
+        a.mb = sw ? nd.nb : nd.mb;
+        a.nb = sw ? nd.mb : nd.nb;
+        a.kb = nd.kb;
+        a.pair_mode = nb.pair_mode;
+        a.swapped = sw ? 1 : 0;
+        a.tile = nb.tile;
+        a.prec = p->opt.precision;
+        std::memcpy(a.posM, sw ? nd.posN : nd.posM, sizeof(a.posM));
+        std::memcpy(a.posN, sw ? nd.posM : nd.posN, sizeof(a.posN));
+        std::memcpy(a.ubit, nb.ubit, sizeof(a.ubit));
+        if (fp16) {
+          // Low word of a node's slot = float bits of its latest evaluation's max.
+          unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + p->off_amax);
+          const uint32_t* leaf_amax = reinterpret_cast<const uint32_t*>(ws + p->off_leaf_amax);
+          auto amax_of = [&](int id) -> const uint32_t* {
+            return p->nodes[id].leaf ? leaf_amax + id : reinterpret_cast<const uint32_t*>(slots + id);
+          };
+          a.amaxA = amax_of(sw ? nd.right : nd.left);
+          a.amaxB = amax_of(sw ? nd.left : nd.right);
+          a.amax_out = slots + T;
+          a.epoch = ++nd.epoch;
+        }
+        const double cmacs = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
+        const double bytes = 8.0 * (double(nvar_of(nd.left)) * na.size() +
+                                    double(nvar_of(nd.right)) * nr.size() +
+                                    double(nb.nvar) * nd.size());
+        if (nb.kernel == XEB_KERNEL_MFMA) {
+          a.pairs = nb.pair_mode == 1 ? reinterpret_cast<const int32_t*>(ws + nb.off_pairs) : nullptr;
+          timed(p, stream, XEB_KERNEL_MFMA, T, cmacs, bytes,
+                [&] { launch_contract_mfma(a, stream); });
+        } else {
+          a.lidx = reinterpret_cast<const int32_t*>(ws + nb.off_lidx);
+          a.ridx = reinterpret_cast<const int32_t*>(ws + nb.off_ridx);
+          timed(p, stream, XEB_KERNEL_GENERIC, T, cmacs, bytes,
+                [&] { launch_contract_generic(a, stream); });
+        }
+        hip_check(hipGetLastError(), "contraction launch");
+        nd.valid = true;
+        nd.cur_key = key;
+        nd.cur_block = bi;
       }
-      hip_check(hipGetLastError(), "contraction launch");
-      nd.valid = true;
-      nd.cur_key = key;
+      const int64_t nk = int64_t(blk.idx.size());
+      const double acc_bytes = double(nk) * (8.0 + 8.0 + 2 * 16.0 + 2 * 16.0);
+      timed(p, stream, XEB_KERNEL_ACCUMULATE, -1, 0.0, acc_bytes, [&] {
+        launch_accumulate(node_ptr(p, p->root, sigma),
+                          reinterpret_cast<const int32_t*>(ws + blk.off_idx),
+                          reinterpret_cast<const int32_t*>(ws + blk.off_rho),
+                          static_cast<double2*>(amps), comp, nk, stream);
+      });
+      hip_check(hipGetLastError(), "accumulate launch");
     }
-    const double acc_bytes = double(p->k) * (8.0 + 4.0 + 2 * 16.0 + 2 * 16.0);
-    timed(p, stream, XEB_KERNEL_ACCUMULATE, 0.0, acc_bytes, [&] {
-      launch_accumulate(node_ptr(p, p->root, sigma), rho, static_cast<double2*>(amps), comp, p->k,
-                        stream);
-    });
-    hip_check(hipGetLastError(), "accumulate launch");
   }
   launch_fold_compensation(static_cast<double2*>(amps), comp, p->k, stream);
   hip_check(hipGetLastError(), "fold launch");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 #include "internal.h"
@@ -11,35 +12,55 @@
 
 namespace xeb {
 
-// A node of the contraction tree (leaf or internal).
-struct Node {
-  bool leaf = true;
-  int left = -1, right = -1, parent = -1;
-  // Tensor legs (internal, unsliced), in layout order: position p of this list
-  // is bit p of the element index inside one variant.
-  std::vector<int32_t> legs;
-  uint64_t outmask = 0;  // qubits whose output leg lies in this subtree
-  uint64_t smask = 0;    // slice-id bits whose leg lies in this subtree
-  int64_t nvar = 1;      // distinct string keys (|t_T| restricted to strings)
-  // Leaf only: string keys (pext of the string on outmask) of each variant.
-  std::vector<uint64_t> leaf_keys;
-  int64_t nslicekeys = 1;  // leaf only: 2^popcount(smask)
-  // Internal only.
-  int mb = 0, nb = 0, kb = 0;
-  std::vector<int32_t> lidx, ridx;  // child variants of each variant
+// An internal node's keys among one block of strings, with the gather maps
+// and the kernel chosen for them.
+struct NodeBlock {
+  int64_t nvar = 1;                 // distinct keys of the node in this block
+  std::vector<int32_t> lidx, ridx;  // child keys of each key (generic kernel)
   int kernel = XEB_KERNEL_GENERIC;
   int pair_mode = 0;                // MFMA: 0 dense, 1 table
   int swapped = 0;                  // MFMA: right child supplies the tile rows
   int tile = 0;                     // MFMA tile shape (see ContractArgs::tile)
   int8_t ubit[16] = {};             // MFMA epilogue write order
   std::vector<int32_t> pairs;       // MFMA table mode: nvarL * nvarR entries
+  uint64_t off_lidx = 0, off_ridx = 0, off_pairs = 0;
+};
+
+// A contiguous range of the distinct strings in lexicographic tuple order.
+struct Block {
+  int64_t first = 0, count = 0;
+  std::vector<NodeBlock> nodes;  // indexed by internal node id - n_leaves
+  std::vector<int32_t> idx;      // positions (in the caller's list) of its strings
+  std::vector<int32_t> rho;      // root key of each of them
+  uint64_t off_idx = 0, off_rho = 0;
+};
+
+// A node of the contraction tree (leaf or internal).
+struct Node {
+  bool leaf = true;
+  int left = -1, right = -1, parent = -1;
+  // Tensor legs (internal, unsliced), in layout order: position p of this list
+  // is bit p of the element index inside one key's tensor.
+  std::vector<int32_t> legs;
+  uint64_t outmask = 0;  // qubits whose output leg lies in this subtree
+  uint64_t smask = 0;    // slice-id bits whose leg lies in this subtree
+  // Leaf only: keys over all strings (pext of the string on outmask).
+  int64_t leaf_nvar = 1;
+  std::vector<uint64_t> leaf_keys;
+  int64_t nslicekeys = 1;  // leaf only: 2^popcount(smask)
+  float leaf_amax = 0.f;   // leaf only: largest |re|, |im| of its table
+  // Internal only.
+  int mb = 0, nb = 0, kb = 0;
   int8_t posM[kMaxBits] = {};
   int8_t posN[kMaxBits] = {};
-  // Device placement (byte offsets inside the workspace).
-  uint64_t off_table = 0, off_lidx = 0, off_ridx = 0, off_pairs = 0;
-  // Resident state: the slice key (sigma & smask) whose table is on device.
+  int64_t table_nvar = 1;  // largest key count over the blocks (table capacity)
+  // Device placement (byte offset inside the workspace).
+  uint64_t off_table = 0;
+  // Resident state: block and slice key (sigma & smask) of the table on device.
   bool valid = false;
   uint64_t cur_key = 0;
+  int cur_block = -1;
+  uint32_t epoch = 0;  // evaluations within the current call (amax epochs)
 
   int64_t size() const { return int64_t(1) << legs.size(); }
 };
@@ -47,6 +68,7 @@ struct Node {
 struct ProfRecord {
   hipEvent_t start, stop;
   int kernel;
+  int node;  // internal node id, -1 for the slice accumulation
   double cmacs, bytes;
 };
 
@@ -59,16 +81,18 @@ struct Plan {
   int n_leaves = 0;
   int root = 0;
   std::vector<Node> nodes;
-  std::vector<int32_t> rho;         // root variant of every input string
-  std::vector<float> leaf_staging;  // all leaf tables, complex64 interleaved
-  uint64_t leaf_bytes = 0;
-  uint64_t off_rho = 0, off_comp = 0, off_scratch = 0, ws_bytes = 0;
+  std::vector<Block> blocks;
+  std::vector<float> staging;  // static region: leaf tables, maps (uploaded at bind)
+  uint64_t off_comp = 0, off_scratch = 0, ws_bytes = 0;
+  uint64_t off_leaf_amax = 0;  // static: float bits of each leaf's largest magnitude
+  uint64_t off_amax = 0;       // dynamic: one (epoch << 32 | bits) slot per node
+  bool capturing = false;      // launches are being captured: no event timing
   void* ws = nullptr;
   uint64_t ws_size = 0;
   xeb_stats_t stats{};
   // Profiling (HIP events around launches).
   bool profiling = false;
-  std::vector<ProfRecord> prof;      // records of the current profiling window
+  std::vector<ProfRecord> prof;  // records of the current profiling window
   std::vector<hipEvent_t> event_pool;
   ~Plan();
 };
@@ -81,11 +105,21 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
 double fidelity_plan(Plan* p, const void* amps, hipStream_t stream);
 
 void hip_check(hipError_t e, const char* what);
+
+struct Batch;
+Batch* create_batch(Plan* const* plans, void* const* amps, int n);
+void launch_batch(Batch* b, hipStream_t stream);
+void batch_fidelities(Batch* b, hipStream_t stream, double* F);
+void destroy_batch(Batch* b);
 void set_profiling(Plan* p, bool on);
-xeb_kernel_profile_t read_profile(Plan* p, int kernel);
+xeb_kernel_profile_t read_profile(Plan* p, int kernel, int node);
 
 }  // namespace xeb
 
 struct xeb_plan {
   xeb::Plan impl;
+};
+
+struct xeb_batch {
+  xeb::Batch* impl = nullptr;
 };

@@ -127,9 +127,21 @@ def node_sets(st: Structure, children, sliced=frozenset()):
     return full, legs, om, sdep
 
 
+# Rates of one MI355X for the time estimate: complex MACs/s on FP32 MFMA
+# (157.3 TFLOP/s / 8) and complex64 elements/s of HBM (8 TB/s / 8 B), plus a
+# fixed cost per launch.
+CMAC_RATE = 157.3e12 / 8
+ELEM_RATE = 8e12 / 8
+LAUNCH_S = 4e-6
+
+
 def tree_cost(st: Structure, children, count: VariantCounter, sliced=(), order=None):
     """Multi-tensor cost over all slices under the executor's schedule, the
-    largest tensor (log2 elements) after slicing, and per-slice cost."""
+    largest tensor (log2 elements) after slicing, per-slice cost, and an
+    estimated time: per evaluation max(C / CMAC_RATE, RW / ELEM_RATE) + launch,
+    with C = k_T 2^(q+r) and RW = |L table| + |R table| + |T table| (Appendix A
+    measures C and RW; the estimate stands in for the efficiency profile the
+    paper suggests in place of log2(C + alpha RW))."""
     sliced = frozenset(sliced)
     bit = {l: j for j, l in enumerate(order)} if order is not None else None
     full, legs, om, sdep = node_sets(st, children, sliced)
@@ -137,11 +149,15 @@ def tree_cost(st: Structure, children, count: VariantCounter, sliced=(), order=N
     s = len(sliced)
     total = 0.0
     per_slice = 0.0
+    seconds = 0.0
     maxsz = max((len(x) for x in legs), default=0)
     for i, (a, b) in enumerate(children):
         t = L + i
         allg = (full[a] | full[b]) - sliced
-        c = count(om[t]) * 2.0 ** len(allg)
+        kt = count(om[t])
+        c = kt * 2.0 ** len(allg)
+        rw = (count(om[a]) * 2.0 ** len(legs[a]) + count(om[b]) * 2.0 ** len(legs[b])
+              + kt * 2.0 ** len(legs[t]))
         per_slice += c
         if not sdep[t]:
             ev = 1.0
@@ -150,13 +166,13 @@ def tree_cost(st: Structure, children, count: VariantCounter, sliced=(), order=N
         else:
             ev = 2.0 ** (s - min(bit[l] for l in sdep[t]))
         total += ev * c
-    return total, maxsz, per_slice
+        seconds += ev * (max(c / CMAC_RATE, rw / ELEM_RATE) + LAUNCH_S)
+    return total, maxsz, per_slice, seconds
 
 
-def greedy_slices(st: Structure, children, count: VariantCounter, n_slice: int,
-                  max_candidates: int = 64):
+def greedy_slices(st: Structure, children, count: VariantCounter, n_slice: int):
     """Add legs one at a time, each the one that most reduces the largest
-    tensor (ties: lower cost)."""
+    tensor (Appendix A, "Slicing"); ties go to the lower estimated time."""
     sliced = set()
     for _ in range(n_slice):
         full, legs, om, sdep = node_sets(st, children, frozenset(sliced))
@@ -168,11 +184,10 @@ def greedy_slices(st: Structure, children, count: VariantCounter, n_slice: int,
         if not cand:
             for x in legs:
                 cand |= x
-        cand = sorted(cand)[: max(max_candidates, 1) * 8]
         best = None
-        for l in cand:
-            tot, mx, _ = tree_cost(st, children, count, sliced | {l})
-            key = (mx, tot, l)
+        for l in sorted(cand):
+            _, mx, _, sec = tree_cost(st, children, count, sliced | {l})
+            key = (mx, sec, l)
             if best is None or key < best[0]:
                 best = (key, l)
         if best is None:
@@ -211,22 +226,27 @@ def order_slices(st: Structure, children, count: VariantCounter, sliced):
 
 
 def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
-         temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True):
-    """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info)."""
+         temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True,
+         objective: str = "time"):
+    """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info).
+
+    Every trial tree is sliced and its slice bits ordered; the kept trial has
+    the lowest estimated time (objective "time") or the fewest complex MACs
+    (objective "cmacs")."""
     st = Structure(circ, fuse_1q, fold_kets)
     count = VariantCounter(bitstrings)
     if st.n_leaves == 1:
-        return [], [], dict(cost=0.0, max_log2=0)
+        return [], [], dict(cost=0.0, max_log2=0, seconds=0.0)
     rng = random.Random(seed)
     best = None
     for t in range(max(trials, 1)):
         ch = greedy_tree(st, count, rng, 0.0 if t == 0 else temp)
-        c, mx, _ = tree_cost(st, ch, count)
-        if best is None or c < best[0]:
-            best = (c, ch)
-    ch = best[1]
-    sliced = greedy_slices(st, ch, count, n_sliced) if n_sliced else []
-    order = order_slices(st, ch, count, sliced) if sliced else []
-    total, mx, per_slice = tree_cost(st, ch, count, order, order)
-    info = dict(cost=total, cost_per_slice=per_slice, max_log2=mx, unsliced_cost=best[0])
-    return ch, order, info
+        unsliced = tree_cost(st, ch, count)[0]
+        sliced = greedy_slices(st, ch, count, n_sliced) if n_sliced else []
+        order = order_slices(st, ch, count, sliced) if sliced else []
+        total, mx, per_slice, sec = tree_cost(st, ch, count, order, order)
+        key = sec if objective == "time" else total
+        if best is None or key < best[0]:
+            best = (key, ch, order, dict(cost=total, cost_per_slice=per_slice, max_log2=mx,
+                                         unsliced_cost=unsliced, seconds=sec, trial=t))
+    return best[1], best[2], best[3]

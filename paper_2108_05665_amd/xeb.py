@@ -84,6 +84,7 @@ class Stats(ctypes.Structure):
         ("rw_elems_full", ctypes.c_double),
         ("evals_full", ctypes.c_double),
         ("workspace_bytes", ctypes.c_uint64),
+        ("n_blocks", ctypes.c_int64),
     ]
 
 
@@ -100,6 +101,7 @@ class NodeStats(ctypes.Structure):
         ("slice_mask", ctypes.c_uint64),
         ("kernel", ctypes.c_int32),
         ("swapped", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
         ("cmacs_per_eval", ctypes.c_double),
     ]
 
@@ -133,6 +135,12 @@ _SIG = {
     "xeb_plan_node_stats": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeStats)]),
     "xeb_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
     "xeb_plan_read_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(KernelProfile)]),
+    "xeb_plan_read_node_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(KernelProfile)]),
+    "xeb_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int32,
+                                        ctypes.POINTER(_P)]),
+    "xeb_batch_launch": (ctypes.c_int, [_P, _P]),
+    "xeb_batch_fidelities": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "xeb_batch_destroy": (ctypes.c_int, [_P]),
     "xeb_plan_destroy": (ctypes.c_int, [_P]),
 }
 for _name, (_res, _args) in _SIG.items():
@@ -295,9 +303,46 @@ class Plan:
         _check(_lib.xeb_plan_read_profile(self._h, KERNEL_IDS[kernel], ctypes.byref(pr)))
         return {name: getattr(pr, name) for name, _ in KernelProfile._fields_}
 
+    def read_node_profile(self, node: int) -> dict:
+        pr = KernelProfile()
+        _check(_lib.xeb_plan_read_node_profile(self._h, int(node), ctypes.byref(pr)))
+        return {name: getattr(pr, name) for name, _ in KernelProfile._fields_}
+
     def close(self):
         if self._h:
             _lib.xeb_plan_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several bound plans replayed as one hipGraph (xeb_batch_*): every launch
+    recomputes all amplitudes of all plans into `amps[i]` and their XEB."""
+
+    def __init__(self, plans, amps=None):
+        self.plans = list(plans)
+        self.amps = list(amps) if amps is not None else [p.new_amps() for p in self.plans]
+        ph = (_P * len(self.plans))(*[p._h for p in self.plans])
+        ah = (_P * len(self.plans))(*[a.data_ptr() for a in self.amps])
+        self._h = _P()
+        _check(_lib.xeb_batch_create(ph, ah, len(self.plans), ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(_lib.xeb_batch_launch(self._h, Plan._stream_handle(stream)))
+
+    def fidelities(self, stream=None):
+        out = (ctypes.c_double * len(self.plans))()
+        _check(_lib.xeb_batch_fidelities(self._h, Plan._stream_handle(stream), out))
+        return [float(x) for x in out]
+
+    def close(self):
+        if self._h:
+            _lib.xeb_batch_destroy(self._h)
             self._h = _P()
 
     def __del__(self):

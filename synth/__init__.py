@@ -13,6 +13,8 @@ from .circuits import (  # noqa: F401
     worked_example_circuit,
     CONFIGS,
     config_circuit,
+    batch_spec,
+    batch_circuit,
 )
 from .bitstrings import (  # noqa: F401
     uniform_bitstrings,

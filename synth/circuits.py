@@ -236,3 +236,24 @@ CONFIGS = {
 
 def config_circuit(name: str) -> Circuit:
     return grid_circuit(**CONFIGS[name])
+
+
+# The batch workload: circuits of uneven size.  Circuit i (seed 1004 + i) takes
+# its grid from BATCH_GRIDS and its cycle count from {10..14}, both drawn with
+# PCG64(1004 + i); its string count is floor(10^u), u uniform in [3, 5), drawn
+# with PCG64(2004 + i).
+BATCH_GRIDS = ((5, 6), (4, 8), (5, 7), (4, 9), (6, 6), (4, 10), (5, 8))
+
+
+def batch_spec(i: int) -> dict:
+    rng = np.random.Generator(np.random.PCG64(1004 + i))
+    rows, cols = BATCH_GRIDS[int(rng.integers(0, len(BATCH_GRIDS)))]
+    cycles = int(rng.integers(10, 15))
+    krng = np.random.Generator(np.random.PCG64(2004 + i))
+    k = int(math.floor(10 ** krng.uniform(3.0, 5.0)))
+    return dict(rows=rows, cols=cols, cycles=cycles, seed=1004 + i, k=k, string_seed=2004 + i)
+
+
+def batch_circuit(i: int) -> Circuit:
+    sp = batch_spec(i)
+    return grid_circuit(sp["rows"], sp["cols"], sp["cycles"], sp["seed"])

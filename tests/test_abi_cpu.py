@@ -151,3 +151,28 @@ def test_planner_tree_is_valid_and_slices_reduce_size():
         assert a < L + i and b < L + i and a not in seen and b not in seen
         seen |= {a, b}
     assert len(seen) == 2 * L - 2
+
+
+def test_memory_budget_splits_strings_into_blocks():
+    """A budget below the one-block workspace makes the dry run cut the sorted
+    strings into contiguous blocks; each block's keys are a subset of the
+    strings' keys, so per-node key sums grow but never exceed the per-block
+    string counts, and the workspace fits the budget."""
+    c = grid_circuit(3, 4, 7, 91)
+    s = uniform_bitstrings(12, 800, 92)
+    ch, sl, _ = planner.plan(c, s, n_sliced=1, trials=2)
+    one = xeb.Plan(c, s, ch, sl, bind=False)
+    st1 = one.stats()
+    assert st1["n_blocks"] == 1
+    budget = st1["workspace_bytes"] * 3 // 4
+    many = xeb.Plan(c, s, ch, sl, memory_budget=budget, bind=False)
+    st = many.stats()
+    assert st["n_blocks"] > 1
+    assert st["workspace_bytes"] <= budget
+    exact = {ns["node"]: ns["variants"] for ns in one.all_node_stats()}
+    for ns in many.all_node_stats():
+        assert ns["variants"] >= exact[ns["node"]]
+        assert ns["variants"] <= st["n_blocks"] * exact[ns["node"]]
+    with pytest.raises(xeb.XebError) as e:
+        xeb.Plan(c, s, ch, sl, memory_budget=1024, bind=False)
+    assert e.value.code == xeb.XEB_ENOMEM

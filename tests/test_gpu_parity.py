@@ -176,3 +176,125 @@ def test_medium_config_sampled_partials():
             assert got[i] == got[first[x]]
         else:
             first[x] = i
+
+
+def test_all_mfma_tile_shapes_vs_state_vector():
+    """Circuits whose plans put nodes on each MFMA tile shape (16-, 32- and
+    64-row tiles, swapped and unswapped), every amplitude checked."""
+    seen = set()
+    cases = [((4, 5, 10), 1500, 10), ((4, 5, 10), 800, 0), ((2, 9, 12), 800, 0)]
+    for shape, k, n_fixed in cases:
+        circ = grid_circuit(*shape, seed=shape[2] * 7 + k)
+        n = circ.n_qubits
+        strings = prefix_bitstrings(n, k, n_fixed, 5) if n_fixed else uniform_bitstrings(n, k, 9)
+        ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+        p, amps = _run(circ, strings, ch, sl)
+        for ns in p.all_node_stats():
+            if ns["kernel"] == "mfma":
+                seen.add((ns["tile"], ns["swapped"]))
+        ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+        assert _rel(amps.cpu().numpy(), ref) <= AMP_TOL, shape
+    assert {(0, 0), (1, 0), (1, 1), (2, 0)} <= seen, seen
+
+
+SPLIT_TOL = 1e-3  # split-precision amplitude bound (normwise)
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+def test_split_precision_vs_state_vector(precision):
+    """Split FP16 / BF16 MFMA products on the small workload and on circuits
+    that exercise every tile shape; every amplitude checked."""
+    cases = [(config_circuit("small_4x5_m8"), config_bitstrings("small_4x5_m8", 20), 0)]
+    for shape, k, n_fixed in [((4, 5, 10), 1500, 10), ((4, 5, 10), 800, 0), ((2, 9, 12), 800, 0)]:
+        circ = grid_circuit(*shape, seed=shape[2] * 7 + k)
+        n = circ.n_qubits
+        s = prefix_bitstrings(n, k, n_fixed, 5) if n_fixed else uniform_bitstrings(n, k, 9)
+        cases.append((circ, s, 2))
+    seen = set()
+    for circ, strings, n_sliced in cases:
+        ch, sl, _ = planner.plan(circ, strings, n_sliced=n_sliced, trials=6)
+        p, amps = _run(circ, strings, ch, sl, precision=precision)
+        seen |= {ns["tile"] for ns in p.all_node_stats() if ns["kernel"] == "mfma"}
+        ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+        got = amps.cpu().numpy()
+        err = _rel(got, ref)
+        print(precision, circ.n_qubits, "rel err", err)
+        assert err <= SPLIT_TOL
+        if precision == "split_fp16":
+            assert err <= 1e-5  # hi/lo FP16 keeps ~22 bits
+        f = p.fidelity(amps)
+        assert abs(f - oxeb.xeb_fidelity(circ.n_qubits, ref)) <= XEB_TOL
+    assert seen == {0, 1, 2}
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+def test_split_medium_sampled_partials(precision):
+    name = "medium_6x6_m12"
+    circ = config_circuit(name)
+    strings = config_bitstrings(name, circ.n_qubits)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=10, trials=16, seed=0)
+    net = build_network(circ)
+    pairs = tn.search_order(tn.closed_leg_sets(net, sl), trials=64)[0]
+    p = xeb.Plan(circ, strings, ch, sl, precision=precision)
+    sigma = 321
+    amps = p.new_amps()
+    p.contract(amps, sigma, sigma + 1)
+    got = amps.cpu().numpy()
+    idx = [1, 5000, 8888]
+    ref = np.array([tn.partial_amplitude(net, int(strings[i]), sl, sigma, pairs=pairs) for i in idx])
+    assert _rel(got[idx], ref) <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_batch_graph_matches_eager_every_replay(precision):
+    """Uneven circuits and batch sizes as one hipGraph: every replay (with eager
+    work and synchronizations in between) equals the eager results bit for bit
+    and the state vector within the amplitude bound."""
+    specs = [((3, 4, 8, 501), 300, 2), ((2, 5, 7, 502), 57, 0), ((4, 4, 6, 503), 1000, 3),
+             ((3, 3, 9, 504), 5, 1)]
+    plans, eager, refs = [], [], []
+    for shape, k, n_sliced in specs:
+        circ = grid_circuit(*shape)
+        strings = uniform_bitstrings(circ.n_qubits, k, shape[-1] + 1)
+        ch, sl, _ = planner.plan(circ, strings, n_sliced=n_sliced, trials=3)
+        p, amps = _run(circ, strings, ch, sl, precision=precision)
+        plans.append(p)
+        eager.append((amps.clone(), p.fidelity(amps)))
+        refs.append(statevec.state_vector(circ)[strings.astype(np.int64)])
+    batch = xeb.Batch(plans)
+    for replay in range(3):
+        for a in batch.amps:
+            a.fill_(123.0)  # stale data must be overwritten by the replay
+        batch.launch()
+        fs = batch.fidelities()
+        torch.cuda.synchronize()
+        for (amps0, f0), got, f, ref in zip(eager, batch.amps, fs, refs):
+            assert torch.equal(got, amps0), replay
+            assert f == f0
+            assert _rel(got.cpu().numpy(), ref) <= AMP_TOL
+        # eager work on the same plans between replays
+        z = plans[0].new_amps()
+        plans[0].contract(z)
+        torch.cuda.synchronize()
+        assert torch.equal(z, eager[0][0])
+    batch.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_string_blocks_match_one_block(precision):
+    """A memory budget that forces several string blocks gives the same
+    amplitudes (state vector within the bound; one-block plan within FP32
+    rounding) and keeps the workspace inside the budget."""
+    circ = grid_circuit(4, 5, 9, 601)
+    strings = uniform_bitstrings(20, 3000, 602)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=3, trials=4)
+    p1, a1 = _run(circ, strings, ch, sl, precision=precision)
+    budget = p1.stats()["workspace_bytes"] // 3
+    pb, ab = _run(circ, strings, ch, sl, precision=precision, memory_budget=budget)
+    assert pb.stats()["n_blocks"] > 1
+    assert pb.stats()["workspace_bytes"] <= budget
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    assert _rel(ab.cpu().numpy(), ref) <= tol
+    assert _rel(ab.cpu().numpy(), a1.cpu().numpy()) <= 1e-5
+    assert abs(pb.fidelity(ab) - p1.fidelity(a1)) <= 1e-6
