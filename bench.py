@@ -104,7 +104,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--trials", type=int, default=16, help="planner trials")
+    ap.add_argument("--trials", type=int, default=16, help="planner greedy trials")
+    ap.add_argument("--anneal-steps", type=int, default=500000, help="tree optimizer steps")
+    ap.add_argument("--anneal-restarts", type=int, default=6)
     ap.add_argument("--precisions", default="split_fp16,c64",
                     help="comma list; the first one gives `value`")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -128,7 +130,9 @@ def main() -> int:
     circ = config_circuit(WORKLOAD)
     strings = config_bitstrings(WORKLOAD, circ.n_qubits)
     t0 = time.perf_counter()
-    children, sliced, info = planner.plan(circ, strings, n_sliced=10, trials=args.trials, seed=0)
+    children, sliced, info = planner.plan(circ, strings, n_sliced=10, trials=args.trials, seed=0,
+                                          anneal_steps=args.anneal_steps,
+                                          anneal_restarts=args.anneal_restarts)
     t_tree = time.perf_counter() - t0
     log(f"planned tree in {t_tree:.1f} s: cost {info['cost']:.3e} cmacs, max 2^{info['max_log2']}")
     n_slices = 1 << len(sliced)

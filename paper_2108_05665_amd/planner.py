@@ -15,7 +15,8 @@ Produces the `contraction_tree` and `sliced_legs` inputs of xeb_plan_create.
   again only when one of its slice bits changes, so the legs that expensive
   nodes depend on get the high bits (greedy from bit 0 upwards).
 
-The simulated-annealing optimizer of Appendix A is not part of this module.
+The local-search optimizer of Appendix A lives in `optimizer` and refines the
+greedy result when `anneal_steps` > 0.
 """
 
 from __future__ import annotations
@@ -52,18 +53,37 @@ class Structure:
 
 
 class VariantCounter:
-    """Number of distinct keys s & mask over the distinct strings (cached)."""
+    """Number of distinct keys s & mask over the distinct strings (cached).
 
-    def __init__(self, bitstrings):
+    Exact for batches of at most `exact_limit` distinct strings.  Larger
+    batches use the expected number of distinct values of k draws over the
+    2^v values of the mask's varying bits (bits that differ somewhere in the
+    batch), which is what the tree search needs; the plan compiler counts
+    exactly."""
+
+    def __init__(self, bitstrings, exact_limit: int = 20000):
         self.s = np.unique(np.asarray(bitstrings, dtype=np.uint64))
         self.cache = {0: 1}
+        self.exact = self.s.size <= exact_limit
+        if self.s.size:
+            self.varying = int(np.bitwise_or.reduce(self.s ^ self.s[0]))
+        else:
+            self.varying = 0
 
     def __call__(self, mask: int) -> int:
         r = self.cache.get(mask)
         if r is None:
-            r = int(np.unique(self.s & np.uint64(mask)).size) if self.s.size else 1
-            self.cache[mask] = max(r, 1)
-            r = self.cache[mask]
+            if not self.s.size:
+                r = 1
+            elif self.exact:
+                r = int(np.unique(self.s & np.uint64(mask)).size)
+            else:
+                v = bin(mask & self.varying).count("1")
+                n_vals = 2.0 ** v
+                k = float(self.s.size)
+                r = int(round(n_vals * -math.expm1(k * math.log1p(-1.0 / n_vals)))) if v else 1
+            r = max(r, 1)
+            self.cache[mask] = r
         return r
 
 
@@ -227,12 +247,17 @@ def order_slices(st: Structure, children, count: VariantCounter, sliced):
 
 def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
          temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True,
-         objective: str = "time"):
+         objective: str = "time", anneal_steps: int = 0, anneal_restarts: int = 4,
+         size_log2_max=None):
     """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info).
 
-    Every trial tree is sliced and its slice bits ordered; the kept trial has
-    the lowest estimated time (objective "time") or the fewest complex MACs
-    (objective "cmacs")."""
+    Every greedy trial tree is sliced and its slice bits ordered; the kept
+    trial has the lowest estimated time (objective "time") or the fewest
+    complex MACs (objective "cmacs").  With anneal_steps > 0 the local-search
+    optimizer (optimizer.anneal) then runs `anneal_restarts` times from the
+    kept tree with different seeds, holding the largest tensor at the greedy
+    tree's size (or `size_log2_max`), and the best result by estimated time
+    under the executor's slice order is returned."""
     st = Structure(circ, fuse_1q, fold_kets)
     count = VariantCounter(bitstrings)
     if st.n_leaves == 1:
@@ -249,4 +274,18 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
         if best is None or key < best[0]:
             best = (key, ch, order, dict(cost=total, cost_per_slice=per_slice, max_log2=mx,
                                          unsliced_cost=unsliced, seconds=sec, trial=t))
+    if anneal_steps > 0:
+        from .optimizer import anneal
+
+        ch0, sl0, info0 = best[1], best[2], best[3]
+        cap = info0["max_log2"] if size_log2_max is None else size_log2_max
+        for r in range(max(anneal_restarts, 1)):
+            ch, sl, _ = anneal(st, count, ch0, sl0, steps=anneal_steps, size_log2_max=cap,
+                               seed=seed * 1000 + r + 1)
+            order = order_slices(st, ch, count, sl) if sl else []
+            total, mx, per_slice, sec = tree_cost(st, ch, count, order, order)
+            if mx <= cap and sec < best[3]["seconds"]:
+                best = (sec, ch, order, dict(cost=total, cost_per_slice=per_slice, max_log2=mx,
+                                             unsliced_cost=tree_cost(st, ch, count)[0],
+                                             seconds=sec, trial=info0["trial"], anneal_restart=r))
     return best[1], best[2], best[3]
