@@ -369,13 +369,64 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     p.off_leaf_amax = off;
     off += align_up(uint64_t(nn) * 4);
     const uint64_t static_end = off;
+    // Node tables.  A table is transient when its parent is only ever
+    // evaluated right after it within the same slice step: then it lives from
+    // its own evaluation to the parent's (ids are post-order) and shares an
+    // arena with other transient tables, packed first-fit by lifetime.  Other
+    // tables are read again later without being recomputed and keep their own
+    // region.
+    const bool many_blocks = blocks.size() > 1;
+    auto transient = [&](int T) {
+      if (T == p.root) return true;
+      const Node& nd = p.nodes[T];
+      const Node& par = p.nodes[nd.parent];
+      const bool slice_ok =
+          par.smask == 0 || (nd.smask != 0 && __builtin_ctzll(nd.smask) == __builtin_ctzll(par.smask));
+      if (!slice_ok) return false;
+      if (!many_blocks || nd.outmask != 0) return true;
+      return par.outmask == 0 && par.smask == 0;
+    };
+    struct Live {
+      int node;
+      int begin, end;  // evaluation positions (node ids) where the table is live
+      uint64_t bytes;
+    };
+    std::vector<Live> lives;
+    uint64_t persistent_end = off;
     for (int T = L; T < nn; ++T) {
       Node& nd = p.nodes[T];
       nd.table_nvar = 1;
       for (const Block& blk : blocks) nd.table_nvar = std::max(nd.table_nvar, blk.nodes[T - L].nvar);
-      nd.off_table = off;
-      off += align_up(uint64_t(nd.table_nvar) * nd.size() * 8);
+      const uint64_t bytes = align_up(uint64_t(nd.table_nvar) * nd.size() * 8);
+      if (transient(T)) {
+        lives.push_back({T, T, T == p.root ? nn : nd.parent, bytes});
+      } else {
+        nd.off_table = persistent_end;
+        persistent_end += bytes;
+      }
     }
+    // First-fit interval packing (largest tables first).
+    std::sort(lives.begin(), lives.end(), [](const Live& x, const Live& y) {
+      return x.bytes != y.bytes ? x.bytes > y.bytes : x.node < y.node;
+    });
+    std::vector<std::pair<uint64_t, const Live*>> placed;  // (arena offset, live)
+    uint64_t arena = 0;
+    for (const Live& lv : lives) {
+      std::vector<std::pair<uint64_t, uint64_t>> busy;  // overlapping [offset, offset + bytes)
+      for (auto& pl : placed)
+        if (pl.second->begin <= lv.end && lv.begin <= pl.second->end)
+          busy.push_back({pl.first, pl.first + pl.second->bytes});
+      std::sort(busy.begin(), busy.end());
+      uint64_t at = 0;
+      for (auto& b : busy) {
+        if (at + lv.bytes <= b.first) break;
+        at = std::max(at, b.second);
+      }
+      placed.push_back({at, &lv});
+      arena = std::max(arena, at + lv.bytes);
+    }
+    for (auto& pl : placed) p.nodes[pl.second->node].off_table = persistent_end + pl.first;
+    off = persistent_end + arena;
     p.off_amax = off;
     off += align_up(uint64_t(nn) * 8);
     p.off_comp = off;
@@ -383,13 +434,21 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     p.off_scratch = off;
     off += kAlign;
     p.ws_bytes = off;
+    if (o.trace > 1)
+      std::fprintf(stderr,
+                   "{\"blocks\":%zu,\"static\":%llu,\"persistent_tables\":%llu,"
+                   "\"arena\":%llu,\"workspace\":%llu}\n",
+                   blocks.size(), (unsigned long long)static_end,
+                   (unsigned long long)(persistent_end - static_end), (unsigned long long)arena,
+                   (unsigned long long)off);
     return static_end;
   };
 
-  // Smallest power-of-two block count that fits; stop when more blocks no
-  // longer shrink the workspace.
+  // Smallest power-of-two block count that fits; give up after three
+  // doublings in a row that do not shrink the workspace below its best.
   uint64_t static_bytes = 0;
-  uint64_t prev_bytes = ~uint64_t(0);
+  uint64_t best_bytes = ~uint64_t(0);
+  int stale = 0;
   for (int64_t nblocks = 1;; nblocks *= 2) {
     if (kd > 0 && nblocks > kd) nblocks = kd;
     std::vector<Block> blocks;
@@ -401,10 +460,15 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     static_bytes = layout(blocks);
     p.blocks = std::move(blocks);
     if (!o.memory_budget || p.ws_bytes <= o.memory_budget) break;
-    if (nblocks >= std::max<int64_t>(kd, 1) || p.ws_bytes >= prev_bytes)
-      fail(XEB_ENOMEM, "workspace of " + std::to_string(p.ws_bytes) +
+    if (p.ws_bytes < best_bytes) {
+      best_bytes = p.ws_bytes;
+      stale = 0;
+    } else {
+      ++stale;
+    }
+    if (nblocks >= std::max<int64_t>(kd, 1) || stale >= 3)
+      fail(XEB_ENOMEM, "workspace of at least " + std::to_string(best_bytes) +
                            " bytes exceeds the budget; more string blocks do not shrink it");
-    prev_bytes = p.ws_bytes;
   }
 
   // ---- leaf tables (FP64 -> complex64) --------------------------------------

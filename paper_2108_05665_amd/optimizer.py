@@ -17,8 +17,11 @@ T): the efficiency-profile objective the paper suggests in place of
 log2(C + alpha RW).  A rotation changes only the terms of u and v, so its
 gain is computed locally (Appendix C, local cost update).  The objective is
     log(total time) + beta * max(log2(largest tensor) - size_log2_max, 0),
-the memory penalty of the paper's f(T) with the largest intermediate as M.
-Acceptance is Metropolis with a geometric temperature schedule.
+the memory penalty of the paper's f(T) with the largest intermediate as M,
+plus, when a byte budget is given, beta * max(log2(tables / budget), 0) with
+tables = sum_T k_T |T| * 8 bytes, the memory of the executor that keeps every
+node's table of keys resident (also a local update: a rotation changes only
+u's table).  Acceptance is Metropolis with a geometric temperature schedule.
 """
 
 from __future__ import annotations
@@ -63,6 +66,7 @@ class TreeState:
         self.k = [1] * n
         self.sdep = [0] * n
         self.term = [0.0] * n
+        self.memv = [0.0] * n
         self.size_hist = {}
         self.recompute_all()
 
@@ -87,6 +91,13 @@ class TreeState:
     def _size_log2(self, v: int) -> int:
         return _popcount(self.legs[v] & ~self.S)
 
+    def _mem(self, v: int) -> float:
+        """Bytes of v's resident table (a leaf's holds every slice key)."""
+        m = 8.0 * self.k[v] * 2.0 ** self._size_log2(v)
+        if v < self.L:
+            m *= 2.0 ** _popcount(self.legs[v] & self.S)
+        return m
+
     def _hist_add(self, e: int, d: int) -> None:
         c = self.size_hist.get(e, 0) + d
         if c:
@@ -99,14 +110,19 @@ class TreeState:
             self.k[j] = self.count(self.om[j])
             self.sdep[j] = self.legs[j] & self.S
         self.size_hist = {}
+        self.mem = 0.0
         for j in range(self.L):
             self._hist_add(self._size_log2(j), 1)
+            self.memv[j] = self._mem(j)
+            self.mem += self.memv[j]
         self.total = 0.0
         for v in range(self.L, 2 * self.L - 1):
             self._refresh(v)
             self.term[v] = self._term(v)
             self.total += self.term[v]
             self._hist_add(self._size_log2(v), 1)
+            self.memv[v] = self._mem(v)
+            self.mem += self.memv[v]
 
     def max_size_log2(self) -> int:
         return max(self.size_hist)
@@ -142,7 +158,8 @@ class TreeState:
         y = self.right[v] if side == 0 else self.left[v]
         g = self.left[u] if pick == 0 else self.right[u]
         undo = (v, u, self.left[v], self.right[v], self.left[u], self.right[u],
-                self.legs[u], self.om[u], self.k[u], self.sdep[u], self.term[u], self.term[v])
+                self.legs[u], self.om[u], self.k[u], self.sdep[u], self.term[u], self.term[v],
+                self.memv[u])
         # u keeps its other child and takes y; v takes u and g (u stays v's child).
         if pick == 0:
             self.left[u] = y
@@ -157,14 +174,19 @@ class TreeState:
         self._hist_add(self._size_log2(u), -1)
         self._refresh(u)
         self._hist_add(self._size_log2(u), 1)
+        m_u = self._mem(u)
+        self.mem += m_u - self.memv[u]
+        self.memv[u] = m_u
         t_u, t_v = self._term(u), self._term(v)
         self.total += t_u + t_v - self.term[u] - self.term[v]
         self.term[u], self.term[v] = t_u, t_v
         return undo
 
     def undo(self, rec) -> None:
-        v, u, lv, rv, lu, ru, legs_u, om_u, k_u, sdep_u, term_u, term_v = rec
+        v, u, lv, rv, lu, ru, legs_u, om_u, k_u, sdep_u, term_u, term_v, mem_u = rec
         self._hist_add(self._size_log2(u), -1)
+        self.mem += mem_u - self.memv[u]
+        self.memv[u] = mem_u
         self.total += term_u + term_v - self.term[u] - self.term[v]
         self.left[v], self.right[v], self.left[u], self.right[u] = lv, rv, lu, ru
         for c in (lv, rv):
@@ -192,7 +214,7 @@ class TreeState:
 
 def anneal(st: Structure, count: VariantCounter, children, sliced=(), steps: int = 100000,
            t0: float = 0.05, t1: float = 0.0005, beta: float = 8.0, size_log2_max=None,
-           slice_every: int = 20000, seed: int = 0):
+           slice_every: int = 20000, seed: int = 0, mem_max=None):
     """Simulated annealing from (children, sliced).  Returns (children, sliced,
     info).  With size_log2_max None the target is the starting tree's largest
     tensor."""
@@ -203,10 +225,13 @@ def anneal(st: Structure, count: VariantCounter, children, sliced=(), steps: int
     n_slice = len(list(sliced))
 
     def objective():
-        return math.log(ts.total) + beta * max(ts.max_size_log2() - size_log2_max, 0)
+        f = math.log(ts.total) + beta * max(ts.max_size_log2() - size_log2_max, 0)
+        if mem_max:
+            f += beta * max(math.log2(ts.mem / mem_max), 0.0)
+        return f
 
     cur = objective()
-    best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2())
+    best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2(), ts.mem)
     internal = list(range(ts.L, 2 * ts.L - 1))
     accepted = 0
     for step in range(steps):
@@ -220,7 +245,7 @@ def anneal(st: Structure, count: VariantCounter, children, sliced=(), steps: int
             cur = new
             accepted += 1
             if cur < best[0]:
-                best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2())
+                best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2(), ts.mem)
         else:
             ts.undo(rec)
         if n_slice and slice_every and (step + 1) % slice_every == 0:
@@ -248,7 +273,7 @@ def anneal(st: Structure, count: VariantCounter, children, sliced=(), steps: int
             ts.set_slices(base | (1 << choice[1]))
             cur = objective()
             if cur < best[0]:
-                best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2())
-    info = dict(objective=best[0], seconds=best[3], max_log2=best[4], accepted=accepted,
-                steps=steps)
+                best = (cur, ts.children(), ts.sliced(), ts.total, ts.max_size_log2(), ts.mem)
+    info = dict(objective=best[0], seconds=best[3], max_log2=best[4], table_bytes=best[5],
+                accepted=accepted, steps=steps)
     return best[1], best[2], info

@@ -245,10 +245,36 @@ def order_slices(st: Structure, children, count: VariantCounter, sliced):
     return order
 
 
+_ANNEAL_CTX = None
+
+
+def _anneal_job(job):
+    from .optimizer import anneal
+
+    st, count = _ANNEAL_CTX
+    return anneal(st, count, **job)
+
+
+def _run_anneals(st, count, jobs, workers):
+    """Runs optimizer.anneal for each job, in order; in forked workers when
+    workers > 1 (each restart is independent and seeded)."""
+    global _ANNEAL_CTX
+    _ANNEAL_CTX = (st, count)
+    try:
+        if workers > 1 and len(jobs) > 1:
+            import multiprocessing as mp
+
+            with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+                return pool.map(_anneal_job, jobs)
+        return [_anneal_job(j) for j in jobs]
+    finally:
+        _ANNEAL_CTX = None
+
+
 def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
          temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True,
          objective: str = "time", anneal_steps: int = 0, anneal_restarts: int = 4,
-         size_log2_max=None):
+         size_log2_max=None, table_bytes_max=None, workers: int = 1):
     """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info).
 
     Every greedy trial tree is sliced and its slice bits ordered; the kept
@@ -257,7 +283,9 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
     optimizer (optimizer.anneal) then runs `anneal_restarts` times from the
     kept tree with different seeds, holding the largest tensor at the greedy
     tree's size (or `size_log2_max`), and the best result by estimated time
-    under the executor's slice order is returned."""
+    under the executor's slice order is returned.  `workers` > 1 runs the
+    restarts in that many forked processes (same results as one process; fork
+    before the process touches the GPU)."""
     st = Structure(circ, fuse_1q, fold_kets)
     count = VariantCounter(bitstrings)
     if st.n_leaves == 1:
@@ -275,17 +303,26 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
             best = (key, ch, order, dict(cost=total, cost_per_slice=per_slice, max_log2=mx,
                                          unsliced_cost=unsliced, seconds=sec, trial=t))
     if anneal_steps > 0:
-        from .optimizer import anneal
-
         ch0, sl0, info0 = best[1], best[2], best[3]
         cap = info0["max_log2"] if size_log2_max is None else size_log2_max
-        for r in range(max(anneal_restarts, 1)):
-            ch, sl, _ = anneal(st, count, ch0, sl0, steps=anneal_steps, size_log2_max=cap,
-                               seed=seed * 1000 + r + 1)
+        jobs = [dict(children=ch0, sliced=sl0, steps=anneal_steps, size_log2_max=cap,
+                     seed=seed * 1000 + r + 1, mem_max=table_bytes_max)
+                for r in range(max(anneal_restarts, 1))]
+        for r, (ch, sl, ainfo) in enumerate(_run_anneals(st, count, jobs, workers)):
             order = order_slices(st, ch, count, sl) if sl else []
             total, mx, per_slice, sec = tree_cost(st, ch, count, order, order)
-            if mx <= cap and sec < best[3]["seconds"]:
+            if table_bytes_max is None:
+                better = mx <= cap and sec < best[3]["seconds"]
+            else:
+                # Prefer fitting the table budget; among trees that do not fit,
+                # prefer less table memory (string blocks absorb the rest).
+                tb, best_tb = ainfo["table_bytes"], best[3].get("table_bytes", float("inf"))
+                fits, best_fits = tb <= table_bytes_max, best_tb <= table_bytes_max
+                better = mx <= cap and ((fits and (not best_fits or sec < best[3]["seconds"]))
+                                        or (not fits and not best_fits and tb < best_tb))
+            if better:
                 best = (sec, ch, order, dict(cost=total, cost_per_slice=per_slice, max_log2=mx,
                                              unsliced_cost=tree_cost(st, ch, count)[0],
-                                             seconds=sec, trial=info0["trial"], anneal_restart=r))
+                                             seconds=sec, trial=info0["trial"], anneal_restart=r,
+                                             table_bytes=ainfo["table_bytes"]))
     return best[1], best[2], best[3]

@@ -285,9 +285,11 @@ def test_string_blocks_match_one_block(precision):
     """A memory budget that forces several string blocks gives the same
     amplitudes (state vector within the bound; one-block plan within FP32
     rounding) and keeps the workspace inside the budget."""
-    circ = grid_circuit(4, 5, 9, 601)
-    strings = uniform_bitstrings(20, 3000, 602)
-    ch, sl, _ = planner.plan(circ, strings, n_sliced=3, trials=4)
+    # Many strings on a shallow circuit: the largest tables hold more keys
+    # than a block has strings, so blocks shrink them (128 blocks at w/3).
+    circ = grid_circuit(4, 5, 7, 641)
+    strings = uniform_bitstrings(20, 20000, 642)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=1, trials=4)
     p1, a1 = _run(circ, strings, ch, sl, precision=precision)
     budget = p1.stats()["workspace_bytes"] // 3
     pb, ab = _run(circ, strings, ch, sl, precision=precision, memory_budget=budget)
