@@ -10,10 +10,14 @@ contraction with the memo tables (all 2^10 slices), the FP64 cross-slice sum
 and the XEB reduction.  Planning (tree, slicing, plan compilation) happens
 once before the timed region and is reported separately.
 
-Both forms run: split-FP16 MFMA products (the headline `value`) and plain
-complex64 on FP32 MFMA, with the speedup and the split-vs-c64 amplitude and
-XEB differences over all strings, and sampled per-slice partials checked
-against the FP64 oracle for each form.
+Both precisions run: split-FP16 MFMA products (the headline `value`) and
+plain complex64 on FP32 MFMA, with the speedup and the split-vs-c64 amplitude
+and XEB differences over all strings, and sampled per-slice partials checked
+against the FP64 oracle for each.  Each precision is timed in two launch
+forms: eager (one host launch per node evaluation) and the hipGraph batch
+form (the same launches captured once, one graph launch per step; `value`).
+The timed steps carry no profiling events; a separate eager pass with HIP
+events on the launch stream gives the per-kernel durations behind `roofline`.
 
 Prints one JSON line.  Progress goes to stderr.
 """
@@ -163,41 +167,66 @@ def main() -> int:
         st = plan.stats()
         amps = plan.new_amps()
 
-        def step():
+        def eager_step():
             amps.zero_()
             plan.contract(amps)
             return plan.fidelity(amps)  # waits for the stream
 
-        for w in range(args.warmup):
-            F = step()
-            log(f"{prec}: warmup {w + 1}/{args.warmup} done, F = {F:.6f}")
+        def timed(step, label):
+            for w in range(args.warmup):
+                step()
+                log(f"{prec} {label}: warmup {w + 1}/{args.warmup} done")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                step()
+                log(f"{prec} {label}: step {k + 1}/{args.steps} done")
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / args.steps
+
+        # Eager form: one launch per node evaluation from the host.
+        sec_eager = timed(eager_step, "eager")
+        F_eager = plan.fidelity(amps)
+        eager_amps = amps.cpu().numpy()
+        # Graph form: the same launches captured once as a hipGraph (zeroing,
+        # contraction, slice sum and XEB in one graph launch).
+        t0 = time.perf_counter()
+        batch = xeb.Batch([plan], [amps])
+        t_capture = time.perf_counter() - t0
+
+        def graph_step():
+            batch.launch()
+
+        sec_graph = timed(graph_step, "graph")
+        F = batch.fidelities()[0]
+        final = amps.cpu().numpy()
+        batch.close()
+        # One more eager pass with HIP events around every launch (outside the
+        # timed region) for the per-kernel durations.
         torch.cuda.synchronize()
         plan.set_profiling(True)
+        eager_step()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            F = step()
-            log(f"{prec}: step {k + 1}/{args.steps} done")
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
         prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate")}
         plan.set_profiling(False)
-        final = amps.cpu().numpy()
         sampled_err = None
         if oracle_ref is not None:
             part = plan.new_amps()
             plan.contract(part, check_sigma, check_sigma + 1)
             got = part.cpu().numpy()[check_idx]
             sampled_err = float(np.linalg.norm(got - oracle_ref) / np.linalg.norm(oracle_ref))
-        sec = elapsed / args.steps
+        sec = sec_graph
         results[prec] = dict(
-            sec=sec, F=F, amps=final, prof=prof, st=st, t_plan=t_plan, sampled_err=sampled_err,
-            amps_per_s=len(strings) / sec,
+            sec=sec, sec_eager=sec_eager, F=F, amps=final, prof=prof, st=st, t_plan=t_plan,
+            t_capture=t_capture, sampled_err=sampled_err,
+            graph_vs_eager_max_abs=float(np.max(np.abs(final - eager_amps))) if len(final) else 0.0,
+            F_eager=F_eager, amps_per_s=len(strings) / sec,
             useful_tflops=8.0 * st["cmacs_full"] / sec / 1e12,
-            share={n: p["seconds"] / args.steps / sec for n, p in prof.items()},
+            share={n: p["seconds"] / max(sum(q["seconds"] for q in prof.values()), 1e-30)
+                   for n, p in prof.items()},
         )
-        log(f"{prec}: {1e3 * sec:.0f} ms/step, {len(strings) / sec:.0f} amplitudes/s, "
-            f"sampled oracle err {sampled_err}")
+        log(f"{prec}: graph {1e3 * sec:.0f} ms/step ({len(strings) / sec:.0f} amplitudes/s), "
+            f"eager {1e3 * sec_eager:.0f} ms/step, sampled oracle err {sampled_err}")
         plan.close()
         del amps
 
@@ -216,6 +245,10 @@ def main() -> int:
     forms = {
         prec: {
             "amplitudes_per_s": x["amps_per_s"], "ms_per_step": 1e3 * x["sec"],
+            "eager_ms_per_step": 1e3 * x["sec_eager"],
+            "eager_amplitudes_per_s": len(strings) / x["sec_eager"],
+            "graph_capture_s": x["t_capture"],
+            "graph_vs_eager_max_abs_diff": x["graph_vs_eager_max_abs"],
             "contraction_tflops_useful": x["useful_tflops"],
             "mfma_frac_useful": x["useful_tflops"] * ISSUED_PER_CMAC[prec] / 8.0 / PEAK_TFLOPS[prec],
             "xeb": x["F"], "sampled_oracle_rel_err": x["sampled_err"],

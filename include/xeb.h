@@ -107,6 +107,10 @@ typedef struct {
   uint64_t memory_budget; /* max workspace bytes, 0 = unlimited (default 0) */
   int32_t trace;          /* >0: print one JSON line per node at plan creation */
   int32_t force_generic;  /* 1: use the generic per-element kernel for every node */
+  int32_t max_ksplit;     /* MFMA split-K chunks per node: 0 = automatic (up to 64),
+                             1 = never split, else a power of two bounding the split */
+  double mfma_min_cmacs;  /* a node evaluation with fewer complex MACs than this (or
+                             fewer than 8 rows) uses the generic kernel; 0 = default 2^23 */
 } xeb_options_t;
 
 typedef struct {
@@ -140,6 +144,7 @@ typedef struct {
   int32_t kernel;            /* XEB_KERNEL_* (first block) */
   int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
   int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256 */
+  int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
   double cmacs_per_eval;     /* |t_T| 2^(q+r) */
 } xeb_node_stats_t;
 

@@ -54,6 +54,8 @@ void xeb_options_default(xeb_options_t* opt) {
   opt->memory_budget = 0;
   opt->trace = 0;
   opt->force_generic = 0;
+  opt->max_ksplit = 0;
+  opt->mfma_min_cmacs = 0.0;
 }
 
 const char* xeb_last_error(void) { return g_last_error.c_str(); }
@@ -164,6 +166,7 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->kernel = nb.kernel;
     st->swapped = nb.kernel == XEB_KERNEL_MFMA ? nb.swapped : 0;
     st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : -1;
+    st->ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
     st->cmacs_per_eval = double(st->variants) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   });
 }

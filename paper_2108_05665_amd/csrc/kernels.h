@@ -34,19 +34,33 @@ struct ContractArgs {
   // row bit ubit[b] (< 32) or column bit ubit[b] - 32.
   int8_t ubit[16];
   int32_t prec;          // MFMA operand precision: XEB_PREC_C64 / _SPLIT_FP16 / _SPLIT_BF16
-  // Largest |re|, |im| of the operand tables (float bits), read for the FP16
-  // scale.  The output's is published as atomicMax((epoch << 32) | bits) into
-  // amax_out, so the latest evaluation (largest epoch) wins without clearing
-  // the slot between evaluations.  NULL: not tracked.
-  const uint32_t* amaxA;
-  const uint32_t* amaxB;
+  // Largest |re|, |im| of the operand tables, read for the FP16 scale.  A
+  // table's value is kept in slots of (epoch << 32) | float bits, kAmaxStride
+  // words apart: amaxA / amaxB point at amax_nA / amax_nB such slots, whose
+  // largest word is the latest evaluation's (largest epoch) maximum.  The
+  // output's is published by atomicMax into slot (workgroup % kAmaxSlots) of
+  // amax_out (workgroup 0 always publishes), so slots never need clearing
+  // between evaluations.  NULL amax_out: not tracked.
+  const unsigned long long* amaxA;
+  const unsigned long long* amaxB;
+  int32_t amax_nA, amax_nB;
   unsigned long long* amax_out;
   uint32_t epoch;
+  // Split K (MFMA): ksplit > 1 cuts K into ksplit equal chunks; the chunk
+  // products go to `partial` ([chunk][tile][BM * BN] complex64, row-major
+  // inside a tile) and a second kernel sums them in chunk order and writes T.
+  int32_t ksplit;
+  float2* partial;
 };
+
+constexpr int kAmaxSlots = 16;   // atomic slots per table
+constexpr int kAmaxStride = 16;  // words between slots (one 128-byte line each)
 
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
 void mfma_tile_shape(int tile, int* bm, int* bn);
+// Tiles of an MFMA contraction with rowsA x rowsB outputs on tile shape `tile`.
+int64_t mfma_tiles(int tile, int64_t rowsA, int64_t rowsB);
 // Queries (once per device) the occupancy the persistent grids use, so that a
 // later stream capture makes no occupancy call.
 void prepare_mfma_launch(int prec);

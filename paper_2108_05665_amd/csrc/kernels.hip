@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
+
 #include "kernels.h"
 
 namespace xeb {
@@ -33,13 +35,31 @@ __device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int nbi
 // Largest |re|, |im| of a wave's values -> one atomicMax per wave on
 // (epoch << 32) | float bits (non-negative floats order like their bits; a
 // later evaluation's larger epoch replaces older values).
-__device__ __forceinline__ void publish_amax(float v, unsigned long long* slot, uint32_t epoch) {
+// Workgroup-wide maximum of v published into the workgroup's slot (called by
+// all 256 threads).
+__device__ __forceinline__ void publish_amax(float v, unsigned long long* slots, uint32_t epoch) {
+  __shared__ float wmax[4];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0)
-    atomicMax(slot, (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    atomicMax(slots + (blockIdx.x % kAmaxSlots) * kAmaxStride,
+              (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(m));
+  }
 }
 
+// Bits of x at positions pos[0..bits) gathered into the low bits (the inverse
+// of deposit).
+__device__ __forceinline__ int64_t extract(int64_t x, const int8_t* pos, int bits) {
+  int64_t r = 0;
+  for (int j = 0; j < bits; ++j) r |= ((x >> pos[j]) & 1) << j;
+  return r;
+}
+
+// Threads walk the output table in its own element order (coalesced stores);
+// each finds the row m and column n its element deposits from.
 __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
   float amax = 0.f;
   const int mn = g.mb + g.nb;
@@ -48,13 +68,12 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
   const int64_t K = int64_t(1) << g.kb;
   const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
   const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
-  const int64_t mmask = (int64_t(1) << g.mb) - 1;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t a = e >> mn;
-    const int64_t rem = e & (per - 1);
-    const int64_t m = rem & mmask;
-    const int64_t n = rem >> g.mb;
+    const int64_t o = e & (per - 1);
+    const int64_t m = extract(o, g.posM, g.mb);
+    const int64_t n = extract(o, g.posN, g.nb);
     const float2* pa = g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb);
     const float2* pb = g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb);
     float re = 0.f, im = 0.f;
@@ -64,7 +83,7 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
       re += x.x * y.x - x.y * y.y;
       im += x.x * y.y + x.y * y.x;
     }
-    g.C[a * per + deposit(m, g.posM, g.mb) + deposit(n, g.posN, g.nb)] = make_float2(re, im);
+    g.C[e] = make_float2(re, im);
     amax = fmaxf(amax, fmaxf(fabsf(re), fabsf(im)));
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
@@ -143,9 +162,15 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Scale exponent e with amax 2^e in [2^14, 2^15) (0 for an all-zero tensor).
-__device__ __forceinline__ int fp16_scale_exp(const uint32_t* slot) {
-  const float m = __uint_as_float(*slot);
+// Scale exponent e with amax 2^e in [2^14, 2^15) (0 for an all-zero tensor),
+// from a table's n amax slots.
+__device__ __forceinline__ int fp16_scale_exp(const unsigned long long* slots, int n) {
+  unsigned long long w = 0;
+  for (int i = 0; i < n; ++i) {
+    const unsigned long long v = slots[i * kAmaxStride];
+    w = v > w ? v : w;
+  }
+  const float m = __uint_as_float(uint32_t(w));
   if (!(m > 0.f)) return 0;
   int e = 14 - ilogbf(m);
   return e < -120 ? -120 : (e > 120 ? 120 : e);
@@ -187,6 +212,74 @@ __device__ __forceinline__ void mma16(const u32x4& a, const u32x4& b, float* acc
 __device__ __forceinline__ u32x4 conj_im(u32x4 w) { return w ^ 0x80000000u; }
 __device__ __forceinline__ u32x4 swap_pair(u32x4 w) { return (w >> 16) | (w << 16); }
 
+// Epilogue set-up shared by the contraction and the split-K reduction:
+// deposit tables of a tile's low row / column bits and this thread's share of
+// the write order (tile element bits 0..7 come from the thread id).
+template <int CFG>
+__device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* dep_m_lo,
+                                               int64_t* dep_n_lo, int& r_tid, int& c_tid) {
+  using T = TileInfo<CFG, 0>;
+  const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
+  const int64_t m_lo_mask = (M < T::BM ? M : T::BM) - 1;
+  const int64_t n_lo_mask = (N < T::BN ? N : T::BN) - 1;
+  for (int i = threadIdx.x; i < T::BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.posM, g.mb);
+  for (int i = threadIdx.x; i < T::BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.posN, g.nb);
+  r_tid = 0;
+  c_tid = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if ((threadIdx.x >> b) & 1) {
+      const int u = g.ubit[b];
+      if (u < 32)
+        r_tid |= 1 << u;
+      else
+        c_tid |= 1 << (u - 32);
+    }
+  }
+}
+
+// Writes a finished tile parked in LDS (Ct, rows of BN + 1) to the output
+// table in the write order ubit; returns the largest |re|, |im| written.
+template <int CFG>
+__device__ __forceinline__ float epilogue_write(const ContractArgs& g, const float2* Ct,
+                                                int64_t row0, int64_t col0,
+                                                const int64_t* dep_m_lo, const int64_t* dep_n_lo,
+                                                int r_tid, int c_tid) {
+  using T = TileInfo<CFG, 0>;
+  constexpr int BM = T::BM, BN = T::BN;
+  const int64_t rowsA = g.nvarA << g.mb;
+  const int64_t rowsB = g.nvarB << g.nb;
+  const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
+  const int64_t sizeC = M * N;
+  const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.posM, g.mb) : 0;
+  const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.posN, g.nb) : 0;
+  float amax = 0.f;
+#pragma unroll 4
+  for (int t = 0; t < T::PER_THREAD; ++t) {
+    int r = r_tid, c = c_tid;
+#pragma unroll
+    for (int b = 8; b < T::UBITS; ++b) {
+      if ((t >> (b - 8)) & 1) {
+        const int u = g.ubit[b];
+        if (u < 32)
+          r |= 1 << u;
+        else
+          c |= 1 << (u - 32);
+      }
+    }
+    const int64_t gr = row0 + r, gc = col0 + c;
+    if (gr >= rowsA || gc >= rowsB) continue;
+    const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
+    int64_t a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
+    if (g.pair_mode == 1) a = g.pairs[a];
+    if (a < 0) continue;
+    const float2 val = Ct[r * (BN + 1) + c];
+    g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = val;
+    amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
+  }
+  return amax;
+}
+
 template <int CFG, int PREC>
 __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   using T = TileInfo<CFG, PREC>;
@@ -212,49 +305,39 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   const int64_t rowsB = g.nvarB << g.nb;
   const int64_t tiles_m = (rowsA + BM - 1) / BM;
   const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
-  const int64_t per_xcd = (tiles + 7) / 8;
+  // Work items: (K chunk, tile), item = chunk * tiles + tile.
+  const int64_t items = tiles * g.ksplit;
+  const int64_t per_xcd = (items + 7) / 8;
   const int64_t walk = per_xcd * 8;
   const int64_t K = int64_t(1) << g.kb;
-  const int64_t M = int64_t(1) << g.mb;
-  const int64_t N = int64_t(1) << g.nb;
-  const int64_t sizeC = M * N;
-  const int64_t m_lo_mask = (M < BM ? M : BM) - 1;
-  const int64_t n_lo_mask = (N < BN ? N : BN) - 1;
+  const int64_t Kc = K / g.ksplit;
 
   // Operand scales (FP16 split only) and the output's rescale.
   int eA = 0, eB = 0;
   if constexpr (PREC == 1) {
-    eA = fp16_scale_exp(g.amaxA);
-    eB = fp16_scale_exp(g.amaxB);
+    eA = fp16_scale_exp(g.amaxA, g.amax_nA);
+    eB = fp16_scale_exp(g.amaxB, g.amax_nB);
   }
   const float sA = ldexpf(1.f, eA), sB = ldexpf(1.f, eB), s_out = ldexpf(1.f, -(eA + eB));
   float amax = 0.f;
 
-  for (int i = tid; i < BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.posM, g.mb);
-  for (int i = tid; i < BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.posN, g.nb);
   int r_tid = 0, c_tid = 0;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    if ((tid >> b) & 1) {
-      const int u = g.ubit[b];
-      if (u < 32)
-        r_tid |= 1 << u;
-      else
-        c_tid |= 1 << (u - 32);
-    }
-  }
+  epilogue_setup<CFG>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
   __syncthreads();
 
-  // Walk position p -> logical tile (XCD-contiguous, column-major).
-  auto tile_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
+  // Walk position p -> work item (XCD-contiguous; tiles column-major inside
+  // one K chunk).
+  auto item_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
   auto next_p = [&](int64_t p) -> int64_t {
     for (p += gridDim.x; p < walk; p += gridDim.x)
-      if (tile_of(p) < tiles) return p;
+      if (item_of(p) < items) return p;
     return walk;
   };
+  auto k_begin = [&](int64_t item) -> int64_t { return (item / tiles) * Kc; };
 
   float4 ra[T::A_VEC], rb[T::B_VEC];
-  auto fetch = [&](int64_t tile, int64_t k0) {
+  auto fetch = [&](int64_t item, int64_t k0) {
+    const int64_t tile = item % tiles;
     const int64_t row0 = (tile % tiles_m) * BM;
     const int64_t col0 = (tile / tiles_m) * BN;
 #pragma unroll
@@ -278,17 +361,19 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   };
 
   int64_t p = blockIdx.x;
-  if (p < walk && tile_of(p) >= tiles) p = next_p(p);
+  if (p < walk && item_of(p) >= items) p = next_p(p);
   if (p >= walk) {
     if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
     return;
   }
-  fetch(tile_of(p), 0);
+  fetch(item_of(p), k_begin(item_of(p)));
 
   while (p < walk) {
-    const int64_t tile = tile_of(p);
+    const int64_t item = item_of(p);
+    const int64_t tile = item % tiles;
     const int64_t row0 = (tile % tiles_m) * BM;
     const int64_t col0 = (tile / tiles_m) * BN;
+    const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
     accv acc_re[T::FM][T::FN], acc_im[T::FM][T::FN];
@@ -302,7 +387,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
           acc_im[fm][fn][v] = 0.f;
         }
 
-    for (int64_t k0 = 0; k0 < K; k0 += TK) {
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
       // Registers -> LDS.
 #pragma unroll
       for (int t = 0; t < T::A_VEC; ++t) {
@@ -335,10 +420,10 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
         }
       }
       __syncthreads();
-      if (k0 + TK < K)
-        fetch(tile, k0 + TK);
+      if (k0 + TK < kend)
+        fetch(item, k0 + TK);
       else if (pn < walk)
-        fetch(tile_of(pn), 0);
+        fetch(item_of(pn), k_begin(item_of(pn)));
 
       if constexpr (PREC == 0 && MF == 32) {
         const int i = lane & 31;
@@ -465,9 +550,32 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
       __syncthreads();
     }
 
-    // Park the tile.  32x32 results: lane l, register v hold row (v % 4) +
-    // 4 (l / 32) + 8 (v / 4), column l % 32.  16x16: row 4 (l / 16) + v,
-    // column l % 16.
+    // 32x32 results: lane l, register v hold row (v % 4) + 4 (l / 32) +
+    // 8 (v / 4), column l % 32.  16x16: row 4 (l / 16) + v, column l % 16.
+    if (g.ksplit > 1) {
+      // A K chunk's product goes to its partial tile, row-major (the last
+      // slab's barrier already freed LDS for the next item).
+      float2* dst = g.partial + item * (BM * BN);
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+          for (int v = 0; v < T::REGS; ++v) {
+            int r, c;
+            if constexpr (MF == 32) {
+              r = wm * T::BMW + fm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+              c = wn * T::BNW + fn * 32 + (lane & 31);
+            } else {
+              r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
+              c = wn * T::BNW + fn * 16 + (lane & 15);
+            }
+            dst[r * BN + c] = make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
+          }
+      p = pn;
+      continue;
+    }
+    // Park the tile in LDS.
 #pragma unroll
     for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -485,33 +593,60 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
           Ct[r * (BN + 1) + c] = make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
         }
     __syncthreads();
-    const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.posM, g.mb) : 0;
-    const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.posN, g.nb) : 0;
-#pragma unroll 4
-    for (int t = 0; t < T::PER_THREAD; ++t) {
-      int r = r_tid, c = c_tid;
-#pragma unroll
-      for (int b = 8; b < T::UBITS; ++b) {
-        if ((t >> (b - 8)) & 1) {
-          const int u = g.ubit[b];
-          if (u < 32)
-            r |= 1 << u;
-          else
-            c |= 1 << (u - 32);
-        }
-      }
-      const int64_t gr = row0 + r, gc = col0 + c;
-      if (gr >= rowsA || gc >= rowsB) continue;
-      const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
-      int64_t a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
-      if (g.pair_mode == 1) a = g.pairs[a];
-      if (a < 0) continue;
-      const float2 val = Ct[r * (BN + 1) + c];
-      g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = val;
-      amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
-    }
+    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
+  }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+}
+
+// Split-K chunk sum: partial[0] += partial[1] + ... + partial[ksplit - 1],
+// element by element in chunk order (deterministic), two complex per thread.
+__global__ void __launch_bounds__(256) k_splitk_sum(float4* partial, int64_t chunk_f4, int ksplit) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < chunk_f4;
+       i += int64_t(gridDim.x) * 256) {
+    float4 acc = partial[i];
+    int kc = 1;
+    for (; kc + 4 <= ksplit; kc += 4) {
+      const float4 a = partial[(kc + 0) * chunk_f4 + i], b = partial[(kc + 1) * chunk_f4 + i];
+      const float4 c = partial[(kc + 2) * chunk_f4 + i], d = partial[(kc + 3) * chunk_f4 + i];
+      acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
+      acc.x += b.x; acc.y += b.y; acc.z += b.z; acc.w += b.w;
+      acc.x += c.x; acc.y += c.y; acc.z += c.z; acc.w += c.w;
+      acc.x += d.x; acc.y += d.y; acc.z += d.z; acc.w += d.w;
+    }
+    for (; kc < ksplit; ++kc) {
+      const float4 a = partial[kc * chunk_f4 + i];
+      acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
+    }
+    partial[i] = acc;
+  }
+}
+
+// Split-K epilogue: each summed tile (chunk 0 of the partials) through LDS to
+// the output in the contraction's write order.  Grid-stride over tiles.
+template <int CFG>
+__global__ void __launch_bounds__(256) k_splitk_reduce(ContractArgs g) {
+  using T = TileInfo<CFG, 0>;
+  constexpr int BM = T::BM, BN = T::BN;
+  __shared__ float2 Ct[BM * (BN + 1)];
+  __shared__ int64_t dep_m_lo[BM];
+  __shared__ int64_t dep_n_lo[BN];
+  const int64_t rowsA = g.nvarA << g.mb;
+  const int64_t rowsB = g.nvarB << g.nb;
+  const int64_t tiles_m = (rowsA + BM - 1) / BM;
+  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  int r_tid = 0, c_tid = 0;
+  epilogue_setup<CFG>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
+  float amax = 0.f;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    for (int e = threadIdx.x; e < BM * BN; e += 256)
+      Ct[(e / BN) * (BN + 1) + (e % BN)] = g.partial[tile * (BM * BN) + e];
+    __syncthreads();
+    const int64_t row0 = (tile % tiles_m) * BM;
+    const int64_t col0 = (tile / tiles_m) * BN;
+    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+    __syncthreads();
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
@@ -605,7 +740,11 @@ inline int grid_for(int64_t work, int block) {
 void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   const int64_t total = a.nvar << (a.mb + a.nb);
   if (total <= 0) return;
-  k_contract_generic<<<grid_for(total, 256), 256, 0, s>>>(a);
+  // Tracking the FP16 scale costs one atomic per workgroup: keep the grid at
+  // a few workgroups per CU then (grid-stride loop).
+  int grid = grid_for(total, 256);
+  if (a.amax_out && grid > 4096) grid = 4096;
+  k_contract_generic<<<grid, 256, 0, s>>>(a);
 }
 
 namespace {
@@ -638,7 +777,14 @@ template <int CFG, int PREC>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, PREC>;
   const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
-  k_contract_mfma<CFG, PREC><<<persistent_grid<CFG, PREC>(tiles), 256, 0, s>>>(a);
+  k_contract_mfma<CFG, PREC><<<persistent_grid<CFG, PREC>(tiles * a.ksplit), 256, 0, s>>>(a);
+  if (a.ksplit > 1) {
+    const int64_t chunk_f4 = tiles * T::BM * T::BN / 2;
+    k_splitk_sum<<<grid_for(chunk_f4, 256), 256, 0, s>>>(reinterpret_cast<float4*>(a.partial),
+                                                         chunk_f4, a.ksplit);
+    const int64_t grid = tiles < 4096 ? tiles : 4096;
+    k_splitk_reduce<CFG><<<unsigned(grid), 256, 0, s>>>(a);
+  }
 }
 
 template <int PREC>
@@ -657,6 +803,8 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   const int64_t rowsA = a.nvarA << a.mb;
   const int64_t rowsB = a.nvarB << a.nb;
   if (rowsA <= 0 || rowsB <= 0) return;
+  if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * TK))))
+    throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
   if (a.prec == 0)
     launch_prec<0>(a, s, rowsA, rowsB);
   else if (a.prec == 1)
@@ -678,6 +826,12 @@ void prepare_mfma_launch(int prec) {
 void mfma_tile_shape(int tile, int* bm, int* bn) {
   *bm = tile == 0 ? 64 : (tile == 1 ? 32 : 16);
   *bn = tile == 0 ? 64 : (tile == 1 ? 128 : 256);
+}
+
+int64_t mfma_tiles(int tile, int64_t rowsA, int64_t rowsB) {
+  int bm = 0, bn = 0;
+  mfma_tile_shape(tile, &bm, &bn);
+  return ((rowsA + bm - 1) / bm) * ((rowsB + bn - 1) / bn);
 }
 
 void launch_zero(void* p, uint64_t bytes, hipStream_t s) {

@@ -81,7 +81,19 @@ void leaves_dfs(const std::vector<Node>& nodes, int t, std::vector<int>& out) {
 // Kernel choice for one node's keys in one block.  MFMA when the stacked GEMM
 // is big enough and its padded tile work stays within 8x the useful MACs; the
 // smaller side supplies the tile rows.
-void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, bool force_generic) {
+// Split K when the tiles alone are far too few for the chip (fewer than 64):
+// double the chunk count until about one work item per CU exists, keeping at
+// least four K slabs (64 complex) per chunk.  With more tiles the extra
+// partial traffic and launches cost more than the added parallelism gains.
+constexpr int64_t kSplitBelowTiles = 64, kSplitItems = 256, kMinChunk = 64;
+
+// Default of xeb_options_t::mfma_min_cmacs: below about 2^23 complex MACs an
+// MFMA launch (persistent grid, LDS staging, ordered epilogue) costs more
+// than the per-element kernel on gfx950.
+constexpr double kMfmaMinCmacs = 8388608.0;
+
+void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, bool force_generic,
+                   int max_ksplit, double min_cmacs) {
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   const double rowsL = double(nvarL) * std::ldexp(1.0, nd.mb);
   const double rowsR = double(nvarR) * std::ldexp(1.0, nd.nb);
@@ -95,10 +107,17 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
   const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
                       std::max(std::ldexp(1.0, nd.kb), double(16));
   nb.kernel = XEB_KERNEL_GENERIC;
-  if (force_generic || nd.kb < 1 || rows < 4 || cols < 64 || useful < 65536.0 ||
+  if (force_generic || nd.kb < 1 || rows < 8 || cols < 64 || useful < min_cmacs ||
       8 * useful < work || pairs > double(1 << 26))
     return;
   nb.kernel = XEB_KERNEL_MFMA;
+  nb.ksplit = 1;
+  const int64_t tiles = mfma_tiles(nb.tile, int64_t(rows), int64_t(cols));
+  const int64_t K = int64_t(1) << nd.kb;
+  const int cap = max_ksplit == 0 ? 64 : max_ksplit;
+  if (tiles < kSplitBelowTiles)
+    while (nb.ksplit < cap && tiles * nb.ksplit < kSplitItems && K / (2 * nb.ksplit) >= kMinChunk)
+      nb.ksplit *= 2;
   // Epilogue write order: tile bits sorted by the output position they feed;
   // bits that select keys come last (columns before rows).
   const int kmb = nb.swapped ? nd.nb : nd.mb, knb = nb.swapped ? nd.mb : nd.nb;
@@ -129,6 +148,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       o.precision != XEB_PREC_SPLIT_BF16)
     fail(XEB_EINVAL, "unknown precision");
   if (o.device < 0) fail(XEB_EINVAL, "device ordinal is negative");
+  if (o.max_ksplit < 0 || o.max_ksplit > 64 || (o.max_ksplit & (o.max_ksplit - 1)))
+    fail(XEB_EINVAL, "max_ksplit must be 0 or a power of two up to 64");
+  if (!(o.mfma_min_cmacs >= 0.0)) fail(XEB_EINVAL, "mfma_min_cmacs must be >= 0");
   p.opt = o;
 
   Net net = build_net(c, o.fuse_1q != 0, o.fold_kets != 0);
@@ -327,7 +349,8 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
         var[T][i] = int32_t(std::lower_bound(uc.begin(), uc.end(), codes[i]) - uc.begin());
       if (!p.nodes[nd.left].leaf) std::vector<int32_t>().swap(var[nd.left]);
       if (!p.nodes[nd.right].leaf) std::vector<int32_t>().swap(var[nd.right]);
-      choose_kernel(nd, nvar_of(nd.left), nr, nb, o.force_generic != 0);
+      choose_kernel(nd, nvar_of(nd.left), nr, nb, o.force_generic != 0, o.max_ksplit,
+                    o.mfma_min_cmacs > 0 ? o.mfma_min_cmacs : kMfmaMinCmacs);
     }
     for (int64_t i = 0; i < k; ++i) {
       const int64_t d = where[i];
@@ -367,7 +390,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       off += align16(blk.rho.size() * 4);
     }
     p.off_leaf_amax = off;
-    off += align_up(uint64_t(nn) * 4);
+    off += align_up(uint64_t(nn) * 8);
     const uint64_t static_end = off;
     // Node tables.  A table is transient when its parent is only ever
     // evaluated right after it within the same slice step: then it lives from
@@ -428,7 +451,24 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     for (auto& pl : placed) p.nodes[pl.second->node].off_table = persistent_end + pl.first;
     off = persistent_end + arena;
     p.off_amax = off;
-    off += align_up(uint64_t(nn) * 8);
+    off += align_up(uint64_t(nn) * kAmaxSlots * kAmaxStride * 8);
+    uint64_t partial = 0;
+    for (const Block& blk : blocks)
+      for (int T = L; T < nn; ++T) {
+        const NodeBlock& nb = blk.nodes[T - L];
+        if (nb.kernel != XEB_KERNEL_MFMA || nb.ksplit == 1) continue;
+        const Node& nd = p.nodes[T];
+        const int64_t nl = p.nodes[nd.left].leaf ? p.nodes[nd.left].leaf_nvar : blk.nodes[nd.left - L].nvar;
+        const int64_t nr = p.nodes[nd.right].leaf ? p.nodes[nd.right].leaf_nvar : blk.nodes[nd.right - L].nvar;
+        int64_t rowsA = nl << nd.mb, rowsB = nr << nd.nb;
+        if (nb.swapped) std::swap(rowsA, rowsB);
+        int bm = 0, bn = 0;
+        mfma_tile_shape(nb.tile, &bm, &bn);
+        partial = std::max<uint64_t>(partial, uint64_t(mfma_tiles(nb.tile, rowsA, rowsB)) * nb.ksplit *
+                                                  uint64_t(bm) * bn * 8);
+      }
+    p.off_partial = off;
+    off += align_up(partial);
     p.off_comp = off;
     off += align_up(uint64_t(k) * 16);
     p.off_scratch = off;
@@ -504,8 +544,12 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
           dst[o2 + 1] = float(x.imag());
           nd.leaf_amax = std::max(nd.leaf_amax, std::max(std::fabs(dst[o2]), std::fabs(dst[o2 + 1])));
         }
-    // Largest magnitude of the leaf table (the FP16 scale of a leaf operand).
-    std::memcpy(p.staging.data() + p.off_leaf_amax / 4 + j, &nd.leaf_amax, 4);
+    // Largest magnitude of the leaf table (the FP16 scale of a leaf operand),
+    // as one amax slot of epoch 0.
+    uint32_t bits32 = 0;
+    std::memcpy(&bits32, &nd.leaf_amax, 4);
+    const uint64_t slot = bits32;
+    std::memcpy(p.staging.data() + p.off_leaf_amax / 4 + 2 * j, &slot, 8);
   }
   auto put = [&](uint64_t off, const std::vector<int32_t>& v) {
     if (!v.empty()) std::memcpy(p.staging.data() + off / 4, v.data(), v.size() * 4);
@@ -693,7 +737,8 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
     nd.cur_block = -1;
   }
   const bool fp16 = p->opt.precision == XEB_PREC_SPLIT_FP16;
-  if (fp16) launch_zero(ws + p->off_amax, uint64_t(p->nodes.size()) * 8, stream);
+  const uint64_t amax_words = uint64_t(kAmaxSlots) * kAmaxStride;
+  if (fp16) launch_zero(ws + p->off_amax, uint64_t(p->nodes.size()) * amax_words * 8, stream);
   const int L = p->n_leaves;
   for (int bi = 0; bi < int(p->blocks.size()); ++bi) {
     const Block& blk = p->blocks[bi];
@@ -727,17 +772,23 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
         std::memcpy(a.posN, sw ? nd.posM : nd.posN, sizeof(a.posN));
         std::memcpy(a.ubit, nb.ubit, sizeof(a.ubit));
         if (fp16) {
-          // Low word of a node's slot = float bits of its latest evaluation's max.
+          // A leaf has one static slot; an internal node kAmaxSlots slots.
           unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + p->off_amax);
-          const uint32_t* leaf_amax = reinterpret_cast<const uint32_t*>(ws + p->off_leaf_amax);
-          auto amax_of = [&](int id) -> const uint32_t* {
-            return p->nodes[id].leaf ? leaf_amax + id : reinterpret_cast<const uint32_t*>(slots + id);
+          const unsigned long long* leaf_amax =
+              reinterpret_cast<const unsigned long long*>(ws + p->off_leaf_amax);
+          const int ida = sw ? nd.right : nd.left, idb = sw ? nd.left : nd.right;
+          auto amax_of = [&](int id) -> const unsigned long long* {
+            return p->nodes[id].leaf ? leaf_amax + id : slots + uint64_t(id) * amax_words;
           };
-          a.amaxA = amax_of(sw ? nd.right : nd.left);
-          a.amaxB = amax_of(sw ? nd.left : nd.right);
-          a.amax_out = slots + T;
+          a.amaxA = amax_of(ida);
+          a.amaxB = amax_of(idb);
+          a.amax_nA = p->nodes[ida].leaf ? 1 : kAmaxSlots;
+          a.amax_nB = p->nodes[idb].leaf ? 1 : kAmaxSlots;
+          a.amax_out = slots + uint64_t(T) * amax_words;
           a.epoch = ++nd.epoch;
         }
+        a.ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
+        a.partial = reinterpret_cast<float2*>(ws + p->off_partial);
         const double cmacs = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
         const double bytes = 8.0 * (double(nvar_of(nd.left)) * na.size() +
                                     double(nvar_of(nd.right)) * nr.size() +

@@ -22,6 +22,7 @@ struct NodeBlock {
   int swapped = 0;                  // MFMA: right child supplies the tile rows
   int tile = 0;                     // MFMA tile shape (see ContractArgs::tile)
   int8_t ubit[16] = {};             // MFMA epilogue write order
+  int ksplit = 1;                   // MFMA: K chunks (partial tiles + reduction)
   std::vector<int32_t> pairs;       // MFMA table mode: nvarL * nvarR entries
   uint64_t off_lidx = 0, off_ridx = 0, off_pairs = 0;
 };
@@ -84,8 +85,9 @@ struct Plan {
   std::vector<Block> blocks;
   std::vector<float> staging;  // static region: leaf tables, maps (uploaded at bind)
   uint64_t off_comp = 0, off_scratch = 0, ws_bytes = 0;
-  uint64_t off_leaf_amax = 0;  // static: float bits of each leaf's largest magnitude
-  uint64_t off_amax = 0;       // dynamic: one (epoch << 32 | bits) slot per node
+  uint64_t off_leaf_amax = 0;  // static: one slot (epoch 0 | float bits) per leaf
+  uint64_t off_amax = 0;       // dynamic: kAmaxSlots (epoch << 32 | bits) slots per node
+  uint64_t off_partial = 0;    // dynamic: split-K partial tiles (largest need of any node)
   bool capturing = false;      // launches are being captured: no event timing
   void* ws = nullptr;
   uint64_t ws_size = 0;

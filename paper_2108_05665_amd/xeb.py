@@ -66,6 +66,8 @@ class Options(ctypes.Structure):
         ("memory_budget", ctypes.c_uint64),
         ("trace", ctypes.c_int32),
         ("force_generic", ctypes.c_int32),
+        ("max_ksplit", ctypes.c_int32),
+        ("mfma_min_cmacs", ctypes.c_double),
     ]
 
 
@@ -102,6 +104,7 @@ class NodeStats(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("swapped", ctypes.c_int32),
         ("tile", ctypes.c_int32),
+        ("ksplit", ctypes.c_int32),
         ("cmacs_per_eval", ctypes.c_double),
     ]
 
@@ -194,7 +197,7 @@ class Plan:
 
     def __init__(self, circ, bitstrings, tree_children, sliced_legs=(), *, fuse_1q=True,
                  fold_kets=True, precision="c64", device=None, memory_budget=0, trace=0,
-                 force_generic=False, bind=True):
+                 force_generic=False, max_ksplit=0, mfma_min_cmacs=0.0, bind=True):
         self._h = _P()
         c, keep = _circuit_struct(circ)
         bs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
@@ -211,6 +214,8 @@ class Plan:
         o.memory_budget = int(memory_budget)
         o.trace = int(trace)
         o.force_generic = int(force_generic)
+        o.max_ksplit = int(max_ksplit)
+        o.mfma_min_cmacs = float(mfma_min_cmacs)
         _check(_lib.xeb_plan_create(ctypes.byref(c), bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                     bs.size, ctypes.byref(tree),
                                     sl.ctypes.data_as(_I32P) if sl.size else None, sl.size,

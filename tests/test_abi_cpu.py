@@ -176,3 +176,52 @@ def test_memory_budget_splits_strings_into_blocks():
     with pytest.raises(xeb.XebError) as e:
         xeb.Plan(c, s, ch, sl, memory_budget=1024, bind=False)
     assert e.value.code == xeb.XEB_ENOMEM
+
+
+def test_split_k_choice_and_option():
+    """Nodes with few tiles and long K are split (reported per node); the
+    option bounds the split and rejects values that are not powers of two."""
+    c = grid_circuit(4, 5, 14, 14 * 7 + 4000)
+    s = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(c, s, n_sliced=2, trials=6)
+    small = dict(mfma_min_cmacs=65536.0)
+    auto = xeb.Plan(c, s, ch, sl, bind=False, **small)
+    ks = [ns["ksplit"] for ns in auto.all_node_stats()]
+    assert max(ks) > 1 and all(k & (k - 1) == 0 for k in ks)
+    for ns in auto.all_node_stats():
+        if ns["ksplit"] > 1:
+            assert ns["kernel"] == "mfma" and (1 << ns["k_bits"]) // ns["ksplit"] >= 64
+    for ns in auto.all_node_stats():
+        if ns["ksplit"] > 1:  # fewer than 64 tiles before the split
+            bm, bn = {0: (64, 64), 1: (32, 128), 2: (16, 256)}[ns["tile"]]
+            rows = ns["left_variants"] << ns["m_bits"]
+            cols = ns["right_variants"] << ns["n_bits"]
+            if ns["swapped"]:
+                rows, cols = cols, rows
+            assert -(-rows // bm) * -(-cols // bn) < 64
+    capped = xeb.Plan(c, s, ch, sl, bind=False, max_ksplit=2, **small)
+    assert max(ns["ksplit"] for ns in capped.all_node_stats()) == 2
+    never = xeb.Plan(c, s, ch, sl, bind=False, max_ksplit=1, **small)
+    assert all(ns["ksplit"] == 1 for ns in never.all_node_stats())
+    for bad in (3, 128, -1):
+        with pytest.raises(xeb.XebError) as e:
+            xeb.Plan(c, s, ch, sl, bind=False, max_ksplit=bad)
+        assert e.value.code == xeb.XEB_EINVAL
+    with pytest.raises(xeb.XebError):
+        xeb.Plan(c, s, ch, sl, bind=False, mfma_min_cmacs=-1.0)
+
+
+def test_kernel_choice_threshold():
+    """Evaluations below mfma_min_cmacs complex MACs, or with fewer than 8
+    rows, use the generic kernel; the default threshold is 2^23."""
+    c = grid_circuit(4, 5, 10, 10 * 7 + 800)
+    s = uniform_bitstrings(20, 800, 9)
+    ch, sl, _ = planner.plan(c, s, n_sliced=2, trials=6)
+    for thr in (0.0, 65536.0, 2.0 ** 20):
+        p = xeb.Plan(c, s, ch, sl, bind=False, mfma_min_cmacs=thr)
+        lim = thr or 2.0 ** 23
+        for ns in p.all_node_stats():
+            if ns["kernel"] == "mfma":
+                assert ns["cmacs_per_eval"] >= lim
+        if thr == 65536.0:
+            assert any(ns["kernel"] == "mfma" for ns in p.all_node_stats())

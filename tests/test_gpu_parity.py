@@ -27,6 +27,10 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 AMP_TOL = 1e-5
 XEB_TOL = 1e-4
+# The default MFMA threshold (2^23 complex MACs per evaluation) leaves few
+# MFMA nodes in circuits of <= 24 qubits; tests that exercise the MFMA paths
+# on such circuits lower it.
+SMALL_MFMA = dict(mfma_min_cmacs=65536.0)
 
 
 def _run(circ, strings, ch, sl, rng=None, **kw):
@@ -64,7 +68,7 @@ def test_small_config_vs_state_vector(force_generic):
     circ = config_circuit("small_4x5_m8")
     strings = config_bitstrings("small_4x5_m8", circ.n_qubits)
     ch, sl, _ = planner.plan(circ, strings, n_sliced=0, trials=8)
-    p, amps = _run(circ, strings, ch, sl, force_generic=force_generic)
+    p, amps = _run(circ, strings, ch, sl, force_generic=force_generic, **SMALL_MFMA)
     kinds = {ns["kernel"] for ns in p.all_node_stats()}
     if force_generic:
         assert kinds == {"generic"}
@@ -188,7 +192,7 @@ def test_all_mfma_tile_shapes_vs_state_vector():
         n = circ.n_qubits
         strings = prefix_bitstrings(n, k, n_fixed, 5) if n_fixed else uniform_bitstrings(n, k, 9)
         ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
-        p, amps = _run(circ, strings, ch, sl)
+        p, amps = _run(circ, strings, ch, sl, **SMALL_MFMA)
         for ns in p.all_node_stats():
             if ns["kernel"] == "mfma":
                 seen.add((ns["tile"], ns["swapped"]))
@@ -213,7 +217,7 @@ def test_split_precision_vs_state_vector(precision):
     seen = set()
     for circ, strings, n_sliced in cases:
         ch, sl, _ = planner.plan(circ, strings, n_sliced=n_sliced, trials=6)
-        p, amps = _run(circ, strings, ch, sl, precision=precision)
+        p, amps = _run(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
         seen |= {ns["tile"] for ns in p.all_node_stats() if ns["kernel"] == "mfma"}
         ref = statevec.state_vector(circ)[strings.astype(np.int64)]
         got = amps.cpu().numpy()
@@ -300,3 +304,27 @@ def test_string_blocks_match_one_block(precision):
     assert _rel(ab.cpu().numpy(), ref) <= tol
     assert _rel(ab.cpu().numpy(), a1.cpu().numpy()) <= 1e-5
     assert abs(pb.fidelity(ab) - p1.fidelity(a1)) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_split_k_matches_unsplit_and_state_vector(precision):
+    """Nodes with few tiles and long K run as K chunks plus a reduction: the
+    amplitudes match the unsplit plan (within FP32 reordering) and the state
+    vector within the bound, and reruns are bit-identical.  The two 20-qubit
+    cases split nodes on all three tile shapes."""
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    seen = set()
+    for cycles, n_sliced in ((14, 2), (16, 0)):
+        circ = grid_circuit(4, 5, cycles, seed=cycles * 7 + 4000)
+        strings = prefix_bitstrings(20, 4000, 12, 5)
+        ch, sl, _ = planner.plan(circ, strings, n_sliced=n_sliced, trials=6)
+        p, a = _run(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
+        seen |= {ns["tile"] for ns in p.all_node_stats() if ns["ksplit"] > 1}
+        _, a2 = _run(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
+        assert torch.equal(a, a2)
+        p1, b = _run(circ, strings, ch, sl, precision=precision, max_ksplit=1, **SMALL_MFMA)
+        assert all(ns["ksplit"] == 1 for ns in p1.all_node_stats())
+        ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+        assert _rel(a.cpu().numpy(), ref) <= tol
+        assert _rel(a.cpu().numpy(), b.cpu().numpy()) <= tol
+    assert seen == {0, 1, 2}, seen
