@@ -80,15 +80,41 @@ def cpu_baseline(net, pairs, strings, sliced, budget_s: float):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", f"contract_mfma_{WORKLOAD}_traffic.json")
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per k_contract_mfma launch from the committed PMC summary, or
+    None when it covers another precision or the kernel / launch sources have
+    changed since the counters were taken."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            doc = json.load(f)
+    except OSError:
+        return None
+    if doc.get("precision") != prec or doc.get("workload") != WORKLOAD:
+        return None
+    for rel, digest in doc["sources_sha256"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return float(doc["bytes_per_launch"])
+
+
 def roofline(prof: dict, prec: str) -> dict:
     mf = prof["mfma"]
     if mf["seconds"] <= 0:
         return {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
+    # Algorithmic work: 8 real FLOP per complex MAC (the split form issues
+    # ISSUED_PER_CMAC of them on its 16-bit MFMAs; reported separately).
+    flops = 8.0 * mf["cmacs"]
     issued = ISSUED_PER_CMAC[prec] * mf["cmacs"]
-    tflops = issued / mf["seconds"] / 1e12
+    tflops = flops / mf["seconds"] / 1e12
     gbs = mf["bytes"] / mf["seconds"] / 1e9
-    ai = issued / mf["bytes"]
+    ai = flops / mf["bytes"]
     ridge = PEAK_TFLOPS[prec] * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai >= ridge:
         r = {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
@@ -96,10 +122,17 @@ def roofline(prof: dict, prec: str) -> dict:
     else:
         r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": gbs / HBM_PEAK_GBS}
-    r.update({"traffic": None, "kernel": "k_contract_mfma",
+    traffic = measured_traffic(prec)
+    bytes_per_launch = mf["bytes"] / max(mf["launches"], 1)
+    r.update({"traffic": traffic, "kernel": "k_contract_mfma",
+              "algorithmic_bytes_per_launch": bytes_per_launch,
+              "algorithmic_flop_per_launch": flops / max(mf["launches"], 1),
+              "issued_flop_per_launch": issued / max(mf["launches"], 1),
+              "issued_tflops": issued / mf["seconds"] / 1e12,
+              "traffic_over_algorithmic": None if traffic is None else traffic / bytes_per_launch,
               "launches": mf["launches"], "avg_launch_us": 1e6 * mf["seconds"] / max(mf["launches"], 1),
-              "issued_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
-              "issued_tflops": tflops, "gbs": gbs})
+              "algorithmic_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
+              "algorithmic_tflops": tflops, "gbs": gbs})
     return r
 
 
@@ -116,6 +149,17 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--plan-only", metavar="PATH",
+                    help="plan the tree and slices, write them to PATH as JSON and exit "
+                         "(no GPU use)")
+    ap.add_argument("--tree", metavar="PATH",
+                    help="take the tree and slices from a --plan-only file instead of "
+                         "planning (no forked optimizer workers, e.g. under a profiler)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the eager form only (value then comes from it)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain scale kernel (read + write of this many MiB) "
+                         "whose HBM counters calibrate the contraction's")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -134,12 +178,34 @@ def main() -> int:
     strings = config_bitstrings(WORKLOAD, circ.n_qubits)
     # Planning forks its optimizer workers, so it runs before the GPU is touched.
     t0 = time.perf_counter()
-    children, sliced, info = planner.plan(circ, strings, n_sliced=10, trials=args.trials, seed=0,
-                                          anneal_steps=args.anneal_steps,
-                                          anneal_restarts=args.anneal_restarts,
-                                          workers=min(args.anneal_restarts, 8))
+    if args.tree:
+        with open(args.tree) as f:
+            saved = json.load(f)
+        assert saved["workload"] == WORKLOAD, saved["workload"]
+        children, sliced, info = saved["children"], saved["sliced"], saved["info"]
+    else:
+        children, sliced, info = planner.plan(circ, strings, n_sliced=10, trials=args.trials,
+                                              seed=0, anneal_steps=args.anneal_steps,
+                                              anneal_restarts=args.anneal_restarts,
+                                              workers=min(args.anneal_restarts, 8))
     t_tree = time.perf_counter() - t0
+    if args.plan_only:
+        with open(args.plan_only, "w") as f:
+            json.dump({"workload": WORKLOAD, "children": [[int(a), int(b)] for a, b in children],
+                       "sliced": [int(x) for x in sliced], "info": info}, f)
+        log(f"tree and slices written to {args.plan_only}")
+        return 0
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mib > 0:
+        # out = 1.0 * src: reads and writes exactly n bytes each, three times.
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration: 3 scale kernels of {n} bytes read + {n} bytes written")
+        del src, dst
     log(f"planned tree in {t_tree:.1f} s: cost {info['cost']:.3e} cmacs, max 2^{info['max_log2']}")
     n_slices = 1 << len(sliced)
 
@@ -190,24 +256,27 @@ def main() -> int:
         eager_amps = amps.cpu().numpy()
         # Graph form: the same launches captured once as a hipGraph (zeroing,
         # contraction, slice sum and XEB in one graph launch).
-        t0 = time.perf_counter()
-        batch = xeb.Batch([plan], [amps])
-        t_capture = time.perf_counter() - t0
+        if args.no_graph:
+            t_capture, sec_graph, F, final = None, None, F_eager, eager_amps
+        else:
+            t0 = time.perf_counter()
+            batch = xeb.Batch([plan], [amps])
+            t_capture = time.perf_counter() - t0
 
-        def graph_step():
-            batch.launch()
+            def graph_step():
+                batch.launch()
 
-        sec_graph = timed(graph_step, "graph")
-        F = batch.fidelities()[0]
-        final = amps.cpu().numpy()
-        batch.close()
+            sec_graph = timed(graph_step, "graph")
+            F = batch.fidelities()[0]
+            final = amps.cpu().numpy()
+            batch.close()
         # One more eager pass with HIP events around every launch (outside the
         # timed region) for the per-kernel durations.
         torch.cuda.synchronize()
         plan.set_profiling(True)
         eager_step()
         torch.cuda.synchronize()
-        prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate")}
+        prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate", "splitk")}
         plan.set_profiling(False)
         sampled_err = None
         if oracle_ref is not None:
@@ -215,7 +284,7 @@ def main() -> int:
             plan.contract(part, check_sigma, check_sigma + 1)
             got = part.cpu().numpy()[check_idx]
             sampled_err = float(np.linalg.norm(got - oracle_ref) / np.linalg.norm(oracle_ref))
-        sec = sec_graph
+        sec = sec_eager if sec_graph is None else sec_graph
         results[prec] = dict(
             sec=sec, sec_eager=sec_eager, F=F, amps=final, prof=prof, st=st, t_plan=t_plan,
             t_capture=t_capture, sampled_err=sampled_err,
@@ -225,7 +294,7 @@ def main() -> int:
             share={n: p["seconds"] / max(sum(q["seconds"] for q in prof.values()), 1e-30)
                    for n, p in prof.items()},
         )
-        log(f"{prec}: graph {1e3 * sec:.0f} ms/step ({len(strings) / sec:.0f} amplitudes/s), "
+        log(f"{prec}: {1e3 * sec:.0f} ms/step ({len(strings) / sec:.0f} amplitudes/s), "
             f"eager {1e3 * sec_eager:.0f} ms/step, sampled oracle err {sampled_err}")
         plan.close()
         del amps
@@ -250,7 +319,8 @@ def main() -> int:
             "graph_capture_s": x["t_capture"],
             "graph_vs_eager_max_abs_diff": x["graph_vs_eager_max_abs"],
             "contraction_tflops_useful": x["useful_tflops"],
-            "mfma_frac_useful": x["useful_tflops"] * ISSUED_PER_CMAC[prec] / 8.0 / PEAK_TFLOPS[prec],
+            "useful_frac_of_mfma_peak": x["useful_tflops"] / PEAK_TFLOPS[prec],
+            "issued_frac_of_mfma_peak": x["useful_tflops"] * ISSUED_PER_CMAC[prec] / 8.0 / PEAK_TFLOPS[prec],
             "xeb": x["F"], "sampled_oracle_rel_err": x["sampled_err"],
             "err_bound": ERR_BOUND[prec], "kernel_time_share": x["share"],
             "roofline": roofline(x["prof"], prec), "plan_compile_s": x["t_plan"],
@@ -279,6 +349,7 @@ def main() -> int:
             "distinct_strings": int(st["k_distinct"]),
             "slices": n_slices,
             "precision": head,
+            "launch_form": "eager" if args.no_graph else "hipgraph",
         },
         "contraction_tflops_useful": r["useful_tflops"],
         "roofline": roofline(r["prof"], head),

@@ -266,12 +266,16 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* stats);
  * xeb_contract record a HIP event pair on its stream around each contraction
  * launch (and around each slice accumulation); 0 stops recording.
  * xeb_plan_read_profile waits for the recorded events and sums, over the
- * launches of one kernel class (XEB_KERNEL_GENERIC, XEB_KERNEL_MFMA, or
- * XEB_KERNEL_ACCUMULATE), the event-measured seconds and the algorithmic
- * work: complex MACs sum |t_T| 2^(q+r) and bytes 8 (|L| + |R| + |T|) of the
- * tables each launch reads and writes (Appendix A, measures C and RW).
+ * launches of one kernel class (XEB_KERNEL_GENERIC, XEB_KERNEL_MFMA,
+ * XEB_KERNEL_ACCUMULATE or XEB_KERNEL_SPLITK), the event-measured seconds and
+ * the algorithmic work: complex MACs sum |t_T| 2^(q+r) and bytes
+ * 8 (|L| + |R| + |T|) of the tables each contraction launch reads and writes
+ * (Appendix A, measures C and RW).  A split-K node's MFMA launch carries that
+ * work; its reduction (chunk sum and epilogue, one event pair) carries the
+ * bytes of the partial tiles it reads plus the table it writes.
  */
 #define XEB_KERNEL_ACCUMULATE 2
+#define XEB_KERNEL_SPLITK 3
 typedef struct {
   int64_t launches;
   double seconds;

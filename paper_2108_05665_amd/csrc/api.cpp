@@ -178,7 +178,7 @@ int xeb_plan_set_profiling(xeb_plan_t plan, int32_t enable) {
 int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t* out) {
   return guarded([&] {
     if (!out) xeb::fail(XEB_EINVAL, "out is NULL");
-    if (kernel < 0 || kernel > XEB_KERNEL_ACCUMULATE) xeb::fail(XEB_EINVAL, "unknown kernel class");
+    if (kernel < 0 || kernel > XEB_KERNEL_SPLITK) xeb::fail(XEB_EINVAL, "unknown kernel class");
     *out = xeb::read_profile(&impl(plan), kernel, -1);
   });
 }

@@ -56,8 +56,21 @@ struct ContractArgs {
 constexpr int kAmaxSlots = 16;   // atomic slots per table
 constexpr int kAmaxStride = 16;  // words between slots (one 128-byte line each)
 
+// Profiling: HIP events attached to the dispatch packets of the next launch
+// group on this thread (hipExtLaunchKernel), so that they time the kernels
+// alone.  The group's first kernel records `start` as it begins, its last
+// kernel `stop` as it ends; each event is cleared once used, and
+// take_launch_events returns the ones no kernel used (the caller records
+// those itself).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+void take_launch_events(hipEvent_t* start, hipEvent_t* stop);
+
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
+// The MFMA contraction; with a.ksplit > 1 it writes the chunk partials only
+// and launch_splitk_reduce (same arguments, same stream, right after) sums
+// them and writes T.
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
+void launch_splitk_reduce(const ContractArgs& a, hipStream_t s);
 void mfma_tile_shape(int tile, int* bm, int* bn);
 // Tiles of an MFMA contraction with rowsA x rowsB outputs on tile shape `tile`.
 int64_t mfma_tiles(int tile, int64_t rowsA, int64_t rowsB);

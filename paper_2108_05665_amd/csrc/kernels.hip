@@ -13,6 +13,7 @@
 // * accumulate / fold_compensation: FP64 Neumaier sum over slices.
 // * xeb: compensated FP64 reduction of sum |amp|^2 in a fixed order.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
@@ -728,6 +729,26 @@ __global__ void __launch_bounds__(XEB_THREADS) k_xeb(const double2* amps, int64_
   }
 }
 
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+thread_local LaunchEvents g_events;
+
+// Launches `kernel`; `first` / `last` mark its place in a timed group.
+template <typename... KArgs, typename... Args>
+void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, bool first, bool last,
+            Args... args) {
+  hipEvent_t a = first ? g_events.start : nullptr;
+  hipEvent_t b = last ? g_events.stop : nullptr;
+  if (a || b) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, static_cast<KArgs>(args)...);
+    if (a) g_events.start = nullptr;
+    if (b) g_events.stop = nullptr;
+  } else {
+    kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
+  }
+}
+
 inline int grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;
@@ -737,6 +758,17 @@ inline int grid_for(int64_t work, int block) {
 
 }  // namespace
 
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_events.start = start;
+  g_events.stop = stop;
+}
+
+void take_launch_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = g_events.start;
+  *stop = g_events.stop;
+  g_events = LaunchEvents{};
+}
+
 void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   const int64_t total = a.nvar << (a.mb + a.nb);
   if (total <= 0) return;
@@ -744,7 +776,7 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   // a few workgroups per CU then (grid-stride loop).
   int grid = grid_for(total, 256);
   if (a.amax_out && grid > 4096) grid = 4096;
-  k_contract_generic<<<grid, 256, 0, s>>>(a);
+  launch(k_contract_generic, dim3(grid), dim3(256), s, true, true, a);
 }
 
 namespace {
@@ -777,14 +809,19 @@ template <int CFG, int PREC>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, PREC>;
   const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
-  k_contract_mfma<CFG, PREC><<<persistent_grid<CFG, PREC>(tiles * a.ksplit), 256, 0, s>>>(a);
-  if (a.ksplit > 1) {
-    const int64_t chunk_f4 = tiles * T::BM * T::BN / 2;
-    k_splitk_sum<<<grid_for(chunk_f4, 256), 256, 0, s>>>(reinterpret_cast<float4*>(a.partial),
-                                                         chunk_f4, a.ksplit);
-    const int64_t grid = tiles < 4096 ? tiles : 4096;
-    k_splitk_reduce<CFG><<<unsigned(grid), 256, 0, s>>>(a);
-  }
+  launch(k_contract_mfma<CFG, PREC>, dim3(persistent_grid<CFG, PREC>(tiles * a.ksplit)), dim3(256), s,
+         true, true, a);
+}
+
+template <int CFG>
+void launch_reduce_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
+  using T = TileInfo<CFG, 0>;
+  const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
+  const int64_t chunk_f4 = tiles * T::BM * T::BN / 2;
+  launch(k_splitk_sum, dim3(grid_for(chunk_f4, 256)), dim3(256), s, true, false,
+         reinterpret_cast<float4*>(a.partial), chunk_f4, a.ksplit);
+  const int64_t grid = tiles < 4096 ? tiles : 4096;
+  launch(k_splitk_reduce<CFG>, dim3(unsigned(grid)), dim3(256), s, false, true, a);
 }
 
 template <int PREC>
@@ -811,6 +848,19 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
     launch_prec<1>(a, s, rowsA, rowsB);
   else
     launch_prec<2>(a, s, rowsA, rowsB);
+}
+
+void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
+  const int64_t rowsA = a.nvarA << a.mb;
+  const int64_t rowsB = a.nvarB << a.nb;
+  if (rowsA <= 0 || rowsB <= 0 || a.ksplit <= 1) return;
+  if (!a.partial) throw std::invalid_argument("split K needs a partial buffer");
+  if (a.tile == 0)
+    launch_reduce_cfg<0>(a, s, rowsA, rowsB);
+  else if (a.tile == 1)
+    launch_reduce_cfg<1>(a, s, rowsA, rowsB);
+  else
+    launch_reduce_cfg<2>(a, s, rowsA, rowsB);
 }
 
 void prepare_mfma_launch(int prec) {
@@ -843,7 +893,8 @@ void launch_zero(void* p, uint64_t bytes, hipStream_t s) {
 void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
                        double2* amps, double2* comp, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  k_accumulate<<<grid_for(n, 256), 256, 0, s>>>(partial, idx, rho, amps, comp, n);
+  launch(k_accumulate, dim3(grid_for(n, 256)), dim3(256), s, true, true, partial, idx, rho, amps,
+         comp, n);
 }
 
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s) {

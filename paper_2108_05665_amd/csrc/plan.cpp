@@ -660,7 +660,9 @@ void recycle_records(Plan* p) {
   p->prof.clear();
 }
 
-// Records an event pair around `launch` when profiling is on.
+// With profiling on, times `launch` (one launch group) by an event pair
+// carried on its kernels' dispatch packets; an event no kernel carried (an
+// empty launch) is recorded on the stream instead, so every pair is valid.
 template <class F>
 void timed(Plan* p, hipStream_t stream, int kernel, int node, double cmacs, double bytes,
            F&& launch) {
@@ -669,9 +671,21 @@ void timed(Plan* p, hipStream_t stream, int kernel, int node, double cmacs, doub
     return;
   }
   ProfRecord r{take_event(p), take_event(p), kernel, node, cmacs, bytes};
-  hip_check(hipEventRecord(r.start, stream), "hipEventRecord");
-  launch();
-  hip_check(hipEventRecord(r.stop, stream), "hipEventRecord");
+  set_launch_events(r.start, r.stop);
+  struct Clear {  // no event stays attached if the launch throws
+    ~Clear() {
+      hipEvent_t a = nullptr, b = nullptr;
+      take_launch_events(&a, &b);
+    }
+  };
+  hipEvent_t start = nullptr, stop = nullptr;
+  {
+    Clear clear;
+    launch();
+    take_launch_events(&start, &stop);
+  }
+  if (start) hip_check(hipEventRecord(start, stream), "hipEventRecord");
+  if (stop) hip_check(hipEventRecord(stop, stream), "hipEventRecord");
   p->prof.push_back(r);
 }
 
@@ -797,6 +811,15 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
           a.pairs = nb.pair_mode == 1 ? reinterpret_cast<const int32_t*>(ws + nb.off_pairs) : nullptr;
           timed(p, stream, XEB_KERNEL_MFMA, T, cmacs, bytes,
                 [&] { launch_contract_mfma(a, stream); });
+          if (a.ksplit > 1) {
+            hip_check(hipGetLastError(), "contraction launch");
+            int bm = 0, bn = 0;
+            mfma_tile_shape(a.tile, &bm, &bn);
+            const double partial = 8.0 * double(mfma_tiles(a.tile, a.nvarA << a.mb, a.nvarB << a.nb)) *
+                                   bm * bn * (a.ksplit + 2);
+            timed(p, stream, XEB_KERNEL_SPLITK, T, 0.0, partial + 8.0 * double(nb.nvar) * nd.size(),
+                  [&] { launch_splitk_reduce(a, stream); });
+          }
         } else {
           a.lidx = reinterpret_cast<const int32_t*>(ws + nb.off_lidx);
           a.ridx = reinterpret_cast<const int32_t*>(ws + nb.off_ridx);

@@ -118,7 +118,7 @@ class KernelProfile(ctypes.Structure):
     ]
 
 
-KERNEL_IDS = {"generic": 0, "mfma": 1, "accumulate": 2}
+KERNEL_IDS = {"generic": 0, "mfma": 1, "accumulate": 2, "splitk": 3}
 
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)

@@ -328,3 +328,32 @@ def test_split_k_matches_unsplit_and_state_vector(precision):
         assert _rel(a.cpu().numpy(), ref) <= tol
         assert _rel(a.cpu().numpy(), b.cpu().numpy()) <= tol
     assert seen == {0, 1, 2}, seen
+
+
+def test_profiling_events_count_every_launch():
+    """With profiling on, every node evaluation and slice accumulation has a
+    valid event pair on its kernels' dispatch packets; counts and algorithmic
+    work match the plan's statistics, the per-node sums add up to the kernel
+    classes' sums, and the amplitudes equal an unprofiled run's."""
+    circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
+    strings = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+    p, ref = _run(circ, strings, ch, sl, **SMALL_MFMA)
+    assert any(ns["ksplit"] > 1 for ns in p.all_node_stats())
+    amps = p.new_amps()
+    p.set_profiling(True)
+    p.contract(amps)
+    torch.cuda.synchronize()
+    assert torch.equal(amps, ref)
+    kinds = {k: p.read_profile(k) for k in ("generic", "mfma", "accumulate", "splitk")}
+    st = p.stats()
+    assert kinds["generic"]["launches"] + kinds["mfma"]["launches"] == st["evals_full"]
+    assert kinds["accumulate"]["launches"] == p.n_slices
+    assert kinds["splitk"]["launches"] >= 1
+    assert abs(kinds["generic"]["cmacs"] + kinds["mfma"]["cmacs"] - st["cmacs_full"]) <= 1e-9 * st["cmacs_full"]
+    for k, pr in kinds.items():
+        assert pr["seconds"] > 0 and pr["seconds"] < 10, (k, pr)
+    per_node = sum(p.read_node_profile(ns["node"])["seconds"] for ns in p.all_node_stats())
+    total = sum(kinds[k]["seconds"] for k in ("generic", "mfma", "splitk"))
+    assert abs(per_node - total) <= 1e-6 * total
+    p.set_profiling(False)
