@@ -155,6 +155,9 @@ def main() -> int:
     ap.add_argument("--tree", metavar="PATH",
                     help="take the tree and slices from a --plan-only file instead of "
                          "planning (no forked optimizer workers, e.g. under a profiler)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the compile-time kernel choices (no per-node autotuning)")
+    ap.add_argument("--autotune-reps", type=int, default=3)
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager form only (value then comes from it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -231,6 +234,12 @@ def main() -> int:
         plan = xeb.Plan(circ, strings, children, sliced, device=0, precision=prec)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
+        tune = None
+        if not args.no_autotune:
+            tune = plan.autotune(reps=args.autotune_reps)
+            log(f"{prec}: autotuned {tune['nodes_tuned']} nodes ({tune['nodes_changed']} changed, "
+                f"{tune['candidates']} candidates) in {tune['tuning_seconds']:.1f} s; model "
+                f"{tune['default_seconds']:.3f} s -> {tune['tuned_seconds']:.3f} s per call")
         amps = plan.new_amps()
 
         def eager_step():
@@ -287,7 +296,7 @@ def main() -> int:
         sec = sec_eager if sec_graph is None else sec_graph
         results[prec] = dict(
             sec=sec, sec_eager=sec_eager, F=F, amps=final, prof=prof, st=st, t_plan=t_plan,
-            t_capture=t_capture, sampled_err=sampled_err,
+            t_capture=t_capture, sampled_err=sampled_err, tune=tune,
             graph_vs_eager_max_abs=float(np.max(np.abs(final - eager_amps))) if len(final) else 0.0,
             F_eager=F_eager, amps_per_s=len(strings) / sec,
             useful_tflops=8.0 * st["cmacs_full"] / sec / 1e12,
@@ -317,6 +326,7 @@ def main() -> int:
             "eager_ms_per_step": 1e3 * x["sec_eager"],
             "eager_amplitudes_per_s": len(strings) / x["sec_eager"],
             "graph_capture_s": x["t_capture"],
+            "autotune": x["tune"],
             "graph_vs_eager_max_abs_diff": x["graph_vs_eager_max_abs"],
             "contraction_tflops_useful": x["useful_tflops"],
             "useful_frac_of_mfma_peak": x["useful_tflops"] / PEAK_TFLOPS[prec],

@@ -288,6 +288,33 @@ int xeb_plan_read_profile(xeb_plan_t plan, int32_t kernel, xeb_kernel_profile_t*
 int xeb_plan_read_node_profile(xeb_plan_t plan, int32_t node, xeb_kernel_profile_t* out);
 
 /*
+ * Autotuning of the contraction kernels (tile shape, row operand, split K, or
+ * the per-element kernel), per internal node.  xeb_plan_autotune times on the
+ * bound workspace, on `stream` (hipStream_t as void*), every configuration
+ * each node's contraction can run with at its real shape and key counts
+ * (first string block): `reps` launches (1..1000) after one warm-up, between
+ * two events.  It keeps the fastest per node; later blocks take the same
+ * choice where they can run it.  The tables in the workspace are
+ * overwritten (the next xeb_contract recomputes them); results do not
+ * change beyond FP32 summation order.  A batch created before tuning keeps
+ * the configuration it captured.  The report (may be NULL):
+ *   default_seconds / tuned_seconds: sum over nodes of the measured launch
+ *   time of the compile-time / chosen configuration times the node's
+ *   evaluations in one call over all 2^s slices (a model of one full call's
+ *   kernel time); tuning_seconds: wall time of the tuning.
+ * Errors: XEB_EINVAL (reps), XEB_ESTATE (no workspace), XEB_EHIP.
+ */
+typedef struct {
+  int32_t nodes_tuned;
+  int32_t nodes_changed;
+  int64_t candidates;
+  double default_seconds;
+  double tuned_seconds;
+  double tuning_seconds;
+} xeb_autotune_report_t;
+int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_report_t* report);
+
+/*
  * Batched form: several bound plans (different circuits, uneven sizes) as one
  * hipGraph.  xeb_batch_create captures, for every plan, the clearing of its
  * amplitude buffer, the contraction of all its 2^s slices (as xeb_contract

@@ -125,6 +125,21 @@ int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* 
   });
 }
 
+int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_report_t* report) {
+  return guarded([&] {
+    const xeb::AutotuneReport r =
+        xeb::autotune_plan(&impl(plan), reps, static_cast<hipStream_t>(stream));
+    if (report) {
+      report->nodes_tuned = r.nodes_tuned;
+      report->nodes_changed = r.nodes_changed;
+      report->candidates = r.candidates;
+      report->default_seconds = r.default_seconds;
+      report->tuned_seconds = r.tuned_seconds;
+      report->tuning_seconds = r.tuning_seconds;
+    }
+  });
+}
+
 int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F) {
   return guarded([&] {
     if (!F) xeb::fail(XEB_EINVAL, "F is NULL");

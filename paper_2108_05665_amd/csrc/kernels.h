@@ -9,12 +9,25 @@ namespace xeb {
 
 constexpr int kMaxBits = 48;  // max legs of one tensor (bits of its element index)
 
+// A set of bit positions (`mask`) with the move masks of the compress /
+// expand method of H. S. Warren, "Hacker's Delight", sections 7-4 and 7-5:
+// mv[i] holds the mask bits that move right by 2^i in the i-th step of
+// gathering the mask's bits to the bottom.  With them, PEXT and PDEP over the
+// mask take six shift-and-mask steps without branches or table loads.
+struct BitMap {
+  uint64_t mask;
+  uint64_t mv[6];
+};
+
 // One pairwise contraction T = L * R over all variants of T (Appendix A:
 // 2^(q+r) complex MACs per variant).  Operand layouts: a variant of L is a
 // row-major (2^mb x 2^kb) matrix (shared legs in the low bits), a variant of
 // R a row-major (2^nb x 2^kb) matrix; element (m, n) of a variant of T lives
-// at offset dep(m, posM) + dep(n, posN), where dep deposits bit j of its
-// argument at bit position pos[j].
+// at offset pdep(m, mapM) + pdep(n, mapN): the row index's bits go, lowest
+// first, to the set bit positions of mapM.mask (the layout keeps each child's
+// free legs in the parent's order, so this is a plain bit deposit), the
+// column index's to those of mapN.mask; the two masks partition the mb + nb
+// bits.
 struct ContractArgs {
   const float2* A;       // L table (variants x 2^(mb+kb))
   const float2* B;       // R table (variants x 2^(nb+kb))
@@ -28,8 +41,8 @@ struct ContractArgs {
   int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table
   int32_t swapped;       // MFMA: rows are R's variants (A <- R, B <- L)
   int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128, 2 = 16 x 256
-  int8_t posM[kMaxBits];
-  int8_t posN[kMaxBits];
+  BitMap mapM;            // output bit positions of the row index's bits
+  BitMap mapN;            // output bit positions of the column index's bits
   // MFMA epilogue write order: bit b of an element's number inside the tile is
   // row bit ubit[b] (< 32) or column bit ubit[b] - 32.
   int8_t ubit[16];

@@ -25,10 +25,15 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
-  int64_t r = 0;
-  for (int j = 0; j < nbits; ++j) r |= ((x >> j) & 1) << pos[j];
-  return r;
+// Bit deposit (PDEP): the low bits of x go, lowest first, to the set bit
+// positions of map.mask; the expand steps of the move-mask method.
+__device__ __forceinline__ int64_t deposit(uint64_t x, const BitMap& map) {
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    const uint64_t t = x << (1 << i);
+    x = (x & ~map.mv[i]) | (t & map.mv[i]);
+  }
+  return int64_t(x & map.mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -53,39 +58,108 @@ __device__ __forceinline__ void publish_amax(float v, unsigned long long* slots,
 
 // Bits of x at positions pos[0..bits) gathered into the low bits (the inverse
 // of deposit).
-__device__ __forceinline__ int64_t extract(int64_t x, const int8_t* pos, int bits) {
-  int64_t r = 0;
-  for (int j = 0; j < bits; ++j) r |= ((x >> pos[j]) & 1) << j;
-  return r;
+// Bit extract (PEXT): the bits of x at the set positions of map.mask,
+// gathered to the bottom; the compress steps of the move-mask method.
+__device__ __forceinline__ int64_t extract(uint64_t x, const BitMap& map) {
+  x &= map.mask;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint64_t t = x & map.mv[i];
+    x = (x ^ t) | (t >> (1 << i));
+  }
+  return int64_t(x);
+}
+
+constexpr int kGenericLog2U = 2;  // outputs per thread in a chunk: 4
+
+
+// Chunks of 256 * U consecutive output elements (a key's table spans whole
+// chunks): thread t takes positions t + 256 u, u < U.  A position's row and
+// column bits split by bit range: the thread id's 8 bits (once per thread),
+// u's bits (once per thread, U values), and the chunk's high bits (once per
+// chunk, wave-uniform).  All U loads are issued before any result is used.
+template <int U, class Dot>
+__device__ __forceinline__ void generic_chunks(const ContractArgs& g, Dot& dot, float& amax) {
+  const int mn = g.mb + g.nb;
+  const int64_t per = int64_t(1) << mn;
+  const int64_t chunks = (g.nvar * per) / (256 * U);
+  const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
+  const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
+  const int64_t m_lo = extract(threadIdx.x, g.mapM);
+  const int64_t n_lo = extract(threadIdx.x, g.mapN);
+  int64_t m_u[U], n_u[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    m_u[u] = extract(int64_t(u) << 8, g.mapM) | m_lo;
+    n_u[u] = extract(int64_t(u) << 8, g.mapN) | n_lo;
+  }
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t e0 = c * (256 * U);
+    const int64_t a = e0 >> mn;
+    const int64_t o_hi = e0 & (per - 1);
+    const int64_t m_hi = extract(o_hi, g.mapM), n_hi = extract(o_hi, g.mapN);
+    const float2* A = g.A + int64_t(g.lidx[a]) * sizeA;
+    const float2* B = g.B + int64_t(g.ridx[a]) * sizeB;
+    float2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = dot(A + ((m_hi | m_u[u]) << g.kb), B + ((n_hi | n_u[u]) << g.kb));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      g.C[e0 + (u << 8) + threadIdx.x] = v[u];
+      amax = fmaxf(amax, fmaxf(fabsf(v[u].x), fabsf(v[u].y)));
+    }
+  }
 }
 
 // Threads walk the output table in its own element order (coalesced stores);
-// each finds the row m and column n its element deposits from.
+// each finds the row m and column n its element deposits from.  Extraction is
+// linear over disjoint bit sets, so when a key's table spans at least one
+// 256-element chunk the thread id's 8 low position bits are extracted once per
+// thread and the chunk's high bits once per chunk (wave-uniform).
 __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
   float amax = 0.f;
   const int mn = g.mb + g.nb;
   const int64_t per = int64_t(1) << mn;
   const int64_t total = g.nvar * per;
-  const int64_t K = int64_t(1) << g.kb;
+  const int K = 1 << g.kb;
   const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
   const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t a = e >> mn;
-    const int64_t o = e & (per - 1);
-    const int64_t m = extract(o, g.posM, g.mb);
-    const int64_t n = extract(o, g.posN, g.nb);
-    const float2* pa = g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb);
-    const float2* pb = g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb);
+  auto dot = [&](const float2* pa, const float2* pb) {
     float re = 0.f, im = 0.f;
+    if (K >= 2) {
+      const float4* qa = reinterpret_cast<const float4*>(pa);
+      const float4* qb = reinterpret_cast<const float4*>(pb);
 #pragma unroll 4
-    for (int64_t k = 0; k < K; ++k) {
-      const float2 x = pa[k], y = pb[k];
-      re += x.x * y.x - x.y * y.y;
-      im += x.x * y.y + x.y * y.x;
+      for (int k = 0; k < K / 2; ++k) {
+        const float4 x = qa[k], y = qb[k];
+        re += x.x * y.x - x.y * y.y;
+        im += x.x * y.y + x.y * y.x;
+        re += x.z * y.z - x.w * y.w;
+        im += x.z * y.w + x.w * y.z;
+      }
+    } else {
+      const float2 x = pa[0], y = pb[0];
+      re = x.x * y.x - x.y * y.y;
+      im = x.x * y.y + x.y * y.x;
     }
-    g.C[e] = make_float2(re, im);
-    amax = fmaxf(amax, fmaxf(fabsf(re), fabsf(im)));
+    return make_float2(re, im);
+  };
+  if (mn >= 8 + kGenericLog2U) {
+    generic_chunks<1 << kGenericLog2U>(g, dot, amax);
+  } else if (mn >= 8) {
+    generic_chunks<1>(g, dot, amax);
+  } else {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+      const int64_t a = e >> mn;
+      const int64_t o = e & (per - 1);
+      const int64_t m = extract(o, g.mapM);
+      const int64_t n = extract(o, g.mapN);
+      const float2 v = dot(g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb),
+                           g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb));
+      g.C[e] = v;
+      amax = fmaxf(amax, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
@@ -223,8 +297,8 @@ __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* d
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t m_lo_mask = (M < T::BM ? M : T::BM) - 1;
   const int64_t n_lo_mask = (N < T::BN ? N : T::BN) - 1;
-  for (int i = threadIdx.x; i < T::BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.posM, g.mb);
-  for (int i = threadIdx.x; i < T::BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.posN, g.nb);
+  for (int i = threadIdx.x; i < T::BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.mapM);
+  for (int i = threadIdx.x; i < T::BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.mapN);
   r_tid = 0;
   c_tid = 0;
 #pragma unroll
@@ -252,8 +326,8 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
   const int64_t rowsB = g.nvarB << g.nb;
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t sizeC = M * N;
-  const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.posM, g.mb) : 0;
-  const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.posN, g.nb) : 0;
+  const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.mapM) : 0;
+  const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.mapN) : 0;
   float amax = 0.f;
 #pragma unroll 4
   for (int t = 0; t < T::PER_THREAD; ++t) {
@@ -773,8 +847,10 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   const int64_t total = a.nvar << (a.mb + a.nb);
   if (total <= 0) return;
   // Tracking the FP16 scale costs one atomic per workgroup: keep the grid at
-  // a few workgroups per CU then (grid-stride loop).
+  // a few workgroups per CU then (grid-stride loop).  With a key spanning
+  // whole 256-element chunks a workgroup takes one chunk per step.
   int grid = grid_for(total, 256);
+  if (a.mb + a.nb >= 8 + kGenericLog2U) grid = int((int64_t(grid) + (1 << kGenericLog2U) - 1) >> kGenericLog2U);
   if (a.amax_out && grid > 4096) grid = 4096;
   launch(k_contract_generic, dim3(grid), dim3(256), s, true, true, a);
 }

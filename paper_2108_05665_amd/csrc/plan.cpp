@@ -42,17 +42,25 @@ uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 // Index arrays (gather maps, string maps) only need 16-byte alignment.
 uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    hip_check(hipGetDevice(&prev), "hipGetDevice");
-    if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+// Move masks of the compress / expand method (H. S. Warren, "Hacker's
+// Delight", 7-4): step i moves the marked bits right by 2^i; mk marks the
+// positions whose count of zero mask bits below them (a parallel suffix over
+// ~mask) has bit i set.
+BitMap bit_map(uint64_t mask) {
+  BitMap b{};
+  b.mask = mask;
+  uint64_t m = mask;
+  uint64_t mk = ~m << 1;
+  for (int i = 0; i < 6; ++i) {
+    uint64_t mp = mk ^ (mk << 1);
+    for (int sh = 2; sh < 64; sh <<= 1) mp ^= mp << sh;
+    const uint64_t mv = mp & m;
+    b.mv[i] = mv;
+    m = (m ^ mv) | (mv >> (1 << i));
+    mk &= ~mp;
   }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
-  }
-};
+  return b;
+}
 
 int rank_in_mask(uint64_t mask, int bit) { return popcount64(mask & ((uint64_t(1) << bit) - 1)); }
 
@@ -86,54 +94,94 @@ void leaves_dfs(const std::vector<Node>& nodes, int t, std::vector<int>& out) {
 // least four K slabs (64 complex) per chunk.  With more tiles the extra
 // partial traffic and launches cost more than the added parallelism gains.
 constexpr int64_t kSplitBelowTiles = 64, kSplitItems = 256, kMinChunk = 64;
+// Split-K partial room reserved for the autotuner's candidates.
+constexpr uint64_t kTunePartialBytes = uint64_t(32) << 20;
 
 // Default of xeb_options_t::mfma_min_cmacs: below about 2^23 complex MACs an
 // MFMA launch (persistent grid, LDS staging, ordered epilogue) costs more
 // than the per-element kernel on gfx950.
 constexpr double kMfmaMinCmacs = 8388608.0;
 
+}  // namespace
+
+bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb) {
+  if (nd.kb < 1) return false;
+  const double pairs = double(nvarL) * double(nvarR);
+  // A sparse pair set pays for padding in the GEMM and for its table: only a
+  // set with at least one key in 8 pairs can run well on MFMA.
+  return pairs <= double(1 << 26) && (nb.nvar == nvarL * nvarR || pairs <= 8.0 * double(nb.nvar));
+}
+
+void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
+                    int ksplit) {
+  nb.kernel = XEB_KERNEL_MFMA;
+  nb.tile = tile;
+  nb.swapped = swapped;
+  nb.ksplit = ksplit;
+  int bm = 0, bn = 0;
+  mfma_tile_shape(tile, &bm, &bn);
+  // Epilogue write order: tile bits sorted by the output position they feed;
+  // bits that select keys come last (columns before rows).
+  const int kmb = swapped ? nd.nb : nd.mb, knb = swapped ? nd.mb : nd.nb;
+  const int8_t* kpm = swapped ? nd.posN : nd.posM;
+  const int8_t* kpn = swapped ? nd.posM : nd.posN;
+  std::vector<std::pair<int, int>> keyed;  // (key, code)
+  for (int j = 0; (1 << j) < bm; ++j) keyed.push_back({j < kmb ? int(kpm[j]) : 2000 + j, j});
+  for (int j = 0; (1 << j) < bn; ++j) keyed.push_back({j < knb ? int(kpn[j]) : 1000 + j, 32 + j});
+  std::sort(keyed.begin(), keyed.end());
+  std::memset(nb.ubit, 0, sizeof(nb.ubit));
+  for (size_t b = 0; b < keyed.size(); ++b) nb.ubit[b] = int8_t(keyed[b].second);
+  nb.pair_mode = (nb.nvar == nvarL * nvarR) ? 0 : 1;
+  (void)nvarR;
+}
+
+void configure_generic(NodeBlock& nb) {
+  nb.kernel = XEB_KERNEL_GENERIC;
+  nb.tile = 0;
+  nb.swapped = 0;
+  nb.ksplit = 1;
+  nb.pair_mode = 0;
+}
+
+int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped) {
+  int64_t rows = nvarL << nd.mb, cols = nvarR << nd.nb;
+  if (swapped) std::swap(rows, cols);
+  return mfma_tiles(tile, rows, cols);
+}
+
+namespace {
+
 void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, bool force_generic,
                    int max_ksplit, double min_cmacs) {
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   const double rowsL = double(nvarL) * std::ldexp(1.0, nd.mb);
   const double rowsR = double(nvarR) * std::ldexp(1.0, nd.nb);
-  const double pairs = double(nvarL) * double(nvarR);
-  nb.swapped = (rowsR < rowsL && rowsR < 64) ? 1 : 0;
-  const double rows = nb.swapped ? rowsR : rowsL;
-  const double cols = nb.swapped ? rowsL : rowsR;
-  nb.tile = rows <= 16 ? 2 : (rows <= 32 ? 1 : 0);
+  const int swapped = (rowsR < rowsL && rowsR < 64) ? 1 : 0;
+  const double rows = swapped ? rowsR : rowsL;
+  const double cols = swapped ? rowsL : rowsR;
+  const int tile = rows <= 16 ? 2 : (rows <= 32 ? 1 : 0);
   int bm = 0, bn = 0;
-  mfma_tile_shape(nb.tile, &bm, &bn);
+  mfma_tile_shape(tile, &bm, &bn);
   const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
                       std::max(std::ldexp(1.0, nd.kb), double(16));
-  nb.kernel = XEB_KERNEL_GENERIC;
-  if (force_generic || nd.kb < 1 || rows < 8 || cols < 64 || useful < min_cmacs ||
-      8 * useful < work || pairs > double(1 << 26))
-    return;
-  nb.kernel = XEB_KERNEL_MFMA;
-  nb.ksplit = 1;
-  const int64_t tiles = mfma_tiles(nb.tile, int64_t(rows), int64_t(cols));
-  const int64_t K = int64_t(1) << nd.kb;
-  const int cap = max_ksplit == 0 ? 64 : max_ksplit;
-  if (tiles < kSplitBelowTiles)
-    while (nb.ksplit < cap && tiles * nb.ksplit < kSplitItems && K / (2 * nb.ksplit) >= kMinChunk)
-      nb.ksplit *= 2;
-  // Epilogue write order: tile bits sorted by the output position they feed;
-  // bits that select keys come last (columns before rows).
-  const int kmb = nb.swapped ? nd.nb : nd.mb, knb = nb.swapped ? nd.mb : nd.nb;
-  const int8_t* kpm = nb.swapped ? nd.posN : nd.posM;
-  const int8_t* kpn = nb.swapped ? nd.posM : nd.posN;
-  std::vector<std::pair<int, int>> keyed;  // (key, code)
-  for (int j = 0; (1 << j) < bm; ++j) keyed.push_back({j < kmb ? int(kpm[j]) : 2000 + j, j});
-  for (int j = 0; (1 << j) < bn; ++j) keyed.push_back({j < knb ? int(kpn[j]) : 1000 + j, 32 + j});
-  std::sort(keyed.begin(), keyed.end());
-  for (size_t b = 0; b < keyed.size(); ++b) nb.ubit[b] = int8_t(keyed[b].second);
-  nb.pair_mode = (nb.nvar == nvarL * nvarR) ? 0 : 1;
-  if (nb.pair_mode == 1) {
+  // Both index forms are kept for nodes either kernel can run, so that the
+  // autotuner may switch between them after compilation.
+  if (mfma_capable(nd, nvarL, nvarR, nb) && nb.nvar != nvarL * nvarR) {
     nb.pairs.assign(size_t(nvarL * nvarR), -1);
     for (int64_t v = 0; v < nb.nvar; ++v)
       nb.pairs[size_t(int64_t(nb.lidx[v]) * nvarR + nb.ridx[v])] = int32_t(v);
   }
+  configure_generic(nb);
+  if (force_generic || !mfma_capable(nd, nvarL, nvarR, nb) || rows < 8 || cols < 64 ||
+      useful < min_cmacs || 8 * useful < work)
+    return;
+  int ksplit = 1;
+  const int64_t tiles = mfma_tiles(tile, int64_t(rows), int64_t(cols));
+  const int64_t K = int64_t(1) << nd.kb;
+  const int cap = max_ksplit == 0 ? 64 : max_ksplit;
+  if (tiles < kSplitBelowTiles)
+    while (ksplit < cap && tiles * ksplit < kSplitItems && K / (2 * ksplit) >= kMinChunk) ksplit *= 2;
+  configure_mfma(nd, nvarL, nvarR, nb, tile, swapped, ksplit);
 }
 
 }  // namespace
@@ -250,6 +298,20 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     nd.kb = int(K.size());
     for (int j = 0; j < nd.mb; ++j) nd.posM[j] = int8_t(pos[M[j]]);
     for (int j = 0; j < nd.nb; ++j) nd.posN[j] = int8_t(pos[N[j]]);
+    // Sorted by parent position, the row and column bits land in increasing
+    // output positions: the kernels' placement is a bit deposit by mask.
+    nd.maskM = nd.maskN = 0;
+    for (int j = 0; j < nd.mb; ++j) {
+      if (j > 0 && nd.posM[j] <= nd.posM[j - 1]) fail(XEB_EINVAL, "internal: row bits out of order");
+      nd.maskM |= uint64_t(1) << nd.posM[j];
+    }
+    for (int j = 0; j < nd.nb; ++j) {
+      if (j > 0 && nd.posN[j] <= nd.posN[j - 1]) fail(XEB_EINVAL, "internal: column bits out of order");
+      nd.maskN |= uint64_t(1) << nd.posN[j];
+    }
+    if ((nd.maskM & nd.maskN) || popcount64(nd.maskM | nd.maskN) != nd.mb + nd.nb ||
+        (nd.mb + nd.nb < 64 && (nd.maskM | nd.maskN) >> (nd.mb + nd.nb)))
+      fail(XEB_EINVAL, "internal: row and column bits do not partition the output");
     for (int32_t x : nd.legs) pos[x] = -1;
     a.legs = K;
     a.legs.insert(a.legs.end(), M.begin(), M.end());
@@ -374,12 +436,11 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     }
     for (Block& blk : blocks) {
       for (NodeBlock& nb : blk.nodes) {
-        if (nb.kernel == XEB_KERNEL_GENERIC) {
-          nb.off_lidx = off;
-          off += align16(uint64_t(nb.nvar) * 4);
-          nb.off_ridx = off;
-          off += align16(uint64_t(nb.nvar) * 4);
-        } else if (nb.pair_mode == 1) {
+        nb.off_lidx = off;
+        off += align16(uint64_t(nb.nvar) * 4);
+        nb.off_ridx = off;
+        off += align16(uint64_t(nb.nvar) * 4);
+        if (!nb.pairs.empty()) {
           nb.off_pairs = off;
           off += align16(nb.pairs.size() * 4);
         }
@@ -451,7 +512,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     for (auto& pl : placed) p.nodes[pl.second->node].off_table = persistent_end + pl.first;
     off = persistent_end + arena;
     p.off_amax = off;
-    off += align_up(uint64_t(nn) * kAmaxSlots * kAmaxStride * 8);
+    if (o.precision == XEB_PREC_SPLIT_FP16) off += align_up(uint64_t(nn) * kAmaxSlots * kAmaxStride * 8);
     uint64_t partial = 0;
     for (const Block& blk : blocks)
       for (int T = L; T < nn; ++T) {
@@ -467,8 +528,20 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
         partial = std::max<uint64_t>(partial, uint64_t(mfma_tiles(nb.tile, rowsA, rowsB)) * nb.ksplit *
                                                   uint64_t(bm) * bn * 8);
       }
+    // Room for the autotuner's split-K candidates on long-K nodes.
+    bool long_k = false;
+    for (const Block& blk : blocks)
+      for (int T = L; T < nn; ++T) {
+        const Node& nd = p.nodes[T];
+        const NodeBlock& nb = blk.nodes[T - L];
+        const int64_t nl = p.nodes[nd.left].leaf ? p.nodes[nd.left].leaf_nvar : blk.nodes[nd.left - L].nvar;
+        const int64_t nr = p.nodes[nd.right].leaf ? p.nodes[nd.right].leaf_nvar : blk.nodes[nd.right - L].nvar;
+        if (nd.kb >= 7 && mfma_capable(nd, nl, nr, nb)) long_k = true;
+      }
+    if (long_k) partial = std::max<uint64_t>(partial, kTunePartialBytes);
     p.off_partial = off;
-    off += align_up(partial);
+    p.partial_bytes = align_up(partial);
+    off += p.partial_bytes;
     p.off_comp = off;
     off += align_up(uint64_t(k) * 16);
     p.off_scratch = off;
@@ -556,12 +629,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   };
   for (Block& blk : p.blocks) {
     for (NodeBlock& nb : blk.nodes) {
-      if (nb.kernel == XEB_KERNEL_GENERIC) {
-        put(nb.off_lidx, nb.lidx);
-        put(nb.off_ridx, nb.ridx);
-      } else if (nb.pair_mode == 1) {
-        put(nb.off_pairs, nb.pairs);
-      }
+      put(nb.off_lidx, nb.lidx);
+      put(nb.off_ridx, nb.ridx);
+      if (!nb.pairs.empty()) put(nb.off_pairs, nb.pairs);
     }
     put(blk.off_idx, blk.idx);
     put(blk.off_rho, blk.rho);
@@ -733,6 +803,69 @@ const float2* node_ptr(const Plan* p, int id, int64_t sigma) {
 
 }  // namespace
 
+int64_t nvar_in(const Plan* p, const Block& blk, int id) {
+  return p->nodes[id].leaf ? p->nodes[id].leaf_nvar : blk.nodes[id - p->n_leaves].nvar;
+}
+
+double evals_per_call(const Plan* p, int T) { return evals_over_all_slices(p->nodes[T].smask, p->s); }
+
+ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
+  char* ws = static_cast<char*>(p->ws);
+  const Node& nd = p->nodes[T];
+  const NodeBlock& nb = blk.nodes[T - p->n_leaves];
+  ContractArgs a{};
+  const bool sw = nb.kernel == XEB_KERNEL_MFMA && nb.swapped;
+  a.A = node_ptr(p, sw ? nd.right : nd.left, sigma);
+  a.B = node_ptr(p, sw ? nd.left : nd.right, sigma);
+  a.C = reinterpret_cast<float2*>(ws + nd.off_table);
+  a.nvar = nb.nvar;
+  a.nvarA = nvar_in(p, blk, sw ? nd.right : nd.left);
+  a.nvarB = nvar_in(p, blk, sw ? nd.left : nd.right);
+  a.mb = sw ? nd.nb : nd.mb;
+  a.nb = sw ? nd.mb : nd.nb;
+  a.kb = nd.kb;
+  a.pair_mode = nb.pair_mode;
+  a.swapped = sw ? 1 : 0;
+  a.tile = nb.tile;
+  a.prec = p->opt.precision;
+  a.mapM = bit_map(sw ? nd.maskN : nd.maskM);
+  a.mapN = bit_map(sw ? nd.maskM : nd.maskN);
+  std::memcpy(a.ubit, nb.ubit, sizeof(a.ubit));
+  if (p->opt.precision == XEB_PREC_SPLIT_FP16) {
+    // A leaf has one static slot; an internal node kAmaxSlots slots.  The
+    // caller sets the epoch.
+    const uint64_t amax_words = uint64_t(kAmaxSlots) * kAmaxStride;
+    unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + p->off_amax);
+    const unsigned long long* leaf_amax = reinterpret_cast<const unsigned long long*>(ws + p->off_leaf_amax);
+    const int ida = sw ? nd.right : nd.left, idb = sw ? nd.left : nd.right;
+    auto amax_of = [&](int id) -> const unsigned long long* {
+      return p->nodes[id].leaf ? leaf_amax + id : slots + uint64_t(id) * amax_words;
+    };
+    a.amaxA = amax_of(ida);
+    a.amaxB = amax_of(idb);
+    a.amax_nA = p->nodes[ida].leaf ? 1 : kAmaxSlots;
+    a.amax_nB = p->nodes[idb].leaf ? 1 : kAmaxSlots;
+    a.amax_out = slots + uint64_t(T) * amax_words;
+  }
+  a.ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
+  a.partial = reinterpret_cast<float2*>(ws + p->off_partial);
+  a.pairs = nb.kernel == XEB_KERNEL_MFMA && nb.pair_mode == 1
+                ? reinterpret_cast<const int32_t*>(ws + nb.off_pairs)
+                : nullptr;
+  a.lidx = reinterpret_cast<const int32_t*>(ws + nb.off_lidx);
+  a.ridx = reinterpret_cast<const int32_t*>(ws + nb.off_ridx);
+  return a;
+}
+
+void launch_node(const ContractArgs& a, const NodeBlock& nb, hipStream_t stream) {
+  if (nb.kernel == XEB_KERNEL_MFMA) {
+    launch_contract_mfma(a, stream);
+    if (a.ksplit > 1) launch_splitk_reduce(a, stream);
+  } else {
+    launch_contract_generic(a, stream);
+  }
+}
+
 void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream) {
   const int64_t total = int64_t(1) << p->s;
   if (b < 0 || e < b || e > total) fail(XEB_EINVAL, "slice range outside [0, 2^s)");
@@ -756,59 +889,19 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
   const int L = p->n_leaves;
   for (int bi = 0; bi < int(p->blocks.size()); ++bi) {
     const Block& blk = p->blocks[bi];
-    auto nvar_of = [&](int id) -> int64_t {
-      return p->nodes[id].leaf ? p->nodes[id].leaf_nvar : blk.nodes[id - L].nvar;
-    };
     for (int64_t sigma = b; sigma < e; ++sigma) {
       for (int T = L; T < int(p->nodes.size()); ++T) {
         Node& nd = p->nodes[T];
         const NodeBlock& nb = blk.nodes[T - L];
         const uint64_t key = uint64_t(sigma) & nd.smask;
         if (nd.valid && nd.cur_key == key && (nd.outmask == 0 || nd.cur_block == bi)) continue;
-        const Node& na = p->nodes[nd.left];
-        const Node& nr = p->nodes[nd.right];
-        ContractArgs a{};
-        const bool sw = nb.kernel == XEB_KERNEL_MFMA && nb.swapped;
-        a.A = node_ptr(p, sw ? nd.right : nd.left, sigma);
-        a.B = node_ptr(p, sw ? nd.left : nd.right, sigma);
-        a.C = reinterpret_cast<float2*>(ws + nd.off_table);
-        a.nvar = nb.nvar;
-        a.nvarA = nvar_of(sw ? nd.right : nd.left);
-        a.nvarB = nvar_of(sw ? nd.left : nd.right);
-        a.mb = sw ? nd.nb : nd.mb;
-        a.nb = sw ? nd.mb : nd.nb;
-        a.kb = nd.kb;
-        a.pair_mode = nb.pair_mode;
-        a.swapped = sw ? 1 : 0;
-        a.tile = nb.tile;
-        a.prec = p->opt.precision;
-        std::memcpy(a.posM, sw ? nd.posN : nd.posM, sizeof(a.posM));
-        std::memcpy(a.posN, sw ? nd.posM : nd.posN, sizeof(a.posN));
-        std::memcpy(a.ubit, nb.ubit, sizeof(a.ubit));
-        if (fp16) {
-          // A leaf has one static slot; an internal node kAmaxSlots slots.
-          unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + p->off_amax);
-          const unsigned long long* leaf_amax =
-              reinterpret_cast<const unsigned long long*>(ws + p->off_leaf_amax);
-          const int ida = sw ? nd.right : nd.left, idb = sw ? nd.left : nd.right;
-          auto amax_of = [&](int id) -> const unsigned long long* {
-            return p->nodes[id].leaf ? leaf_amax + id : slots + uint64_t(id) * amax_words;
-          };
-          a.amaxA = amax_of(ida);
-          a.amaxB = amax_of(idb);
-          a.amax_nA = p->nodes[ida].leaf ? 1 : kAmaxSlots;
-          a.amax_nB = p->nodes[idb].leaf ? 1 : kAmaxSlots;
-          a.amax_out = slots + uint64_t(T) * amax_words;
-          a.epoch = ++nd.epoch;
-        }
-        a.ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
-        a.partial = reinterpret_cast<float2*>(ws + p->off_partial);
+        ContractArgs a = node_args(p, blk, T, sigma);
+        if (fp16) a.epoch = ++nd.epoch;
         const double cmacs = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
-        const double bytes = 8.0 * (double(nvar_of(nd.left)) * na.size() +
-                                    double(nvar_of(nd.right)) * nr.size() +
+        const double bytes = 8.0 * (double(nvar_in(p, blk, nd.left)) * p->nodes[nd.left].size() +
+                                    double(nvar_in(p, blk, nd.right)) * p->nodes[nd.right].size() +
                                     double(nb.nvar) * nd.size());
         if (nb.kernel == XEB_KERNEL_MFMA) {
-          a.pairs = nb.pair_mode == 1 ? reinterpret_cast<const int32_t*>(ws + nb.off_pairs) : nullptr;
           timed(p, stream, XEB_KERNEL_MFMA, T, cmacs, bytes,
                 [&] { launch_contract_mfma(a, stream); });
           if (a.ksplit > 1) {
@@ -821,8 +914,6 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
                   [&] { launch_splitk_reduce(a, stream); });
           }
         } else {
-          a.lidx = reinterpret_cast<const int32_t*>(ws + nb.off_lidx);
-          a.ridx = reinterpret_cast<const int32_t*>(ws + nb.off_ridx);
           timed(p, stream, XEB_KERNEL_GENERIC, T, cmacs, bytes,
                 [&] { launch_contract_generic(a, stream); });
         }

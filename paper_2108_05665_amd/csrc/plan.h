@@ -54,6 +54,7 @@ struct Node {
   int mb = 0, nb = 0, kb = 0;
   int8_t posM[kMaxBits] = {};
   int8_t posN[kMaxBits] = {};
+  uint64_t maskM = 0, maskN = 0;  // the same positions as bit masks
   int64_t table_nvar = 1;  // largest key count over the blocks (table capacity)
   // Device placement (byte offset inside the workspace).
   uint64_t off_table = 0;
@@ -87,7 +88,8 @@ struct Plan {
   uint64_t off_comp = 0, off_scratch = 0, ws_bytes = 0;
   uint64_t off_leaf_amax = 0;  // static: one slot (epoch 0 | float bits) per leaf
   uint64_t off_amax = 0;       // dynamic: kAmaxSlots (epoch << 32 | bits) slots per node
-  uint64_t off_partial = 0;    // dynamic: split-K partial tiles (largest need of any node)
+  uint64_t off_partial = 0;    // dynamic: split-K partial tiles
+  uint64_t partial_bytes = 0;  // their capacity (largest need, or the tuning reserve)
   bool capturing = false;      // launches are being captured: no event timing
   void* ws = nullptr;
   uint64_t ws_size = 0;
@@ -107,6 +109,42 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
 double fidelity_plan(Plan* p, const void* amps, hipStream_t stream);
 
 void hip_check(hipError_t e, const char* what);
+
+// Makes `dev` current for the scope and restores the previous device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    hip_check(hipGetDevice(&prev), "hipGetDevice");
+    if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Kernel configuration of one node in one block (compile-time choice or the
+// autotuner's).
+bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
+void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
+                    int ksplit);
+void configure_generic(NodeBlock& nb);
+int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped);
+// Key count of node `id` in block `blk` (a leaf's: all its keys).
+int64_t nvar_in(const Plan* p, const Block& blk, int id);
+// Arguments of internal node T's contraction for slice sigma in block blk.
+ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma);
+// Launches that contraction (both kernels of a split-K node) on `stream`.
+void launch_node(const ContractArgs& a, const NodeBlock& nb, hipStream_t stream);
+// Evaluations of a node over one call covering all 2^s slices.
+double evals_per_call(const Plan* p, int T);
+
+struct AutotuneReport {
+  int nodes_tuned = 0, nodes_changed = 0;
+  int64_t candidates = 0;
+  double default_seconds = 0, tuned_seconds = 0, tuning_seconds = 0;
+};
+AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream);
 
 struct Batch;
 Batch* create_batch(Plan* const* plans, void* const* amps, int n);

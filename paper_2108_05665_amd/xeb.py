@@ -120,6 +120,17 @@ class KernelProfile(ctypes.Structure):
 
 KERNEL_IDS = {"generic": 0, "mfma": 1, "accumulate": 2, "splitk": 3}
 
+class AutotuneReport(ctypes.Structure):
+    _fields_ = [
+        ("nodes_tuned", ctypes.c_int32),
+        ("nodes_changed", ctypes.c_int32),
+        ("candidates", ctypes.c_int64),
+        ("default_seconds", ctypes.c_double),
+        ("tuned_seconds", ctypes.c_double),
+        ("tuning_seconds", ctypes.c_double),
+    ]
+
+
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _SIG = {
@@ -134,6 +145,7 @@ _SIG = {
     "xeb_plan_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "xeb_contract": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "xeb_fidelity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "xeb_plan_autotune": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(AutotuneReport)]),
     "xeb_plan_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "xeb_plan_node_stats": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeStats)]),
     "xeb_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -302,6 +314,12 @@ class Plan:
     # -- measurement -------------------------------------------------------------
     def set_profiling(self, enable: bool) -> None:
         _check(_lib.xeb_plan_set_profiling(self._h, int(bool(enable))))
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        """xeb_plan_autotune: per-node kernel configuration by measurement."""
+        r = AutotuneReport()
+        _check(_lib.xeb_plan_autotune(self._h, int(reps), self._stream_handle(stream), ctypes.byref(r)))
+        return {name: getattr(r, name) for name, _ in AutotuneReport._fields_}
 
     def read_profile(self, kernel: str) -> dict:
         pr = KernelProfile()

@@ -357,3 +357,48 @@ def test_profiling_events_count_every_launch():
     total = sum(kinds[k]["seconds"] for k in ("generic", "mfma", "splitk"))
     assert abs(per_node - total) <= 1e-6 * total
     p.set_profiling(False)
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_autotune_keeps_results(precision):
+    """The autotuner times every configuration of every node and keeps the
+    fastest (never slower than the compile-time choice in its own model);
+    amplitudes stay within the bound of the state vector and of the untuned
+    plan, graph replays still equal eager runs bit for bit, and a plan with
+    string blocks applies the choice to every block."""
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
+    strings = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    p, a0 = _run(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
+    before = [(ns["kernel"], ns["tile"], ns["swapped"], ns["ksplit"]) for ns in p.all_node_stats()]
+    rep = p.autotune(reps=2)
+    assert rep["nodes_tuned"] == len(ch) and rep["candidates"] >= len(ch)
+    assert rep["tuned_seconds"] <= rep["default_seconds"]
+    after = [(ns["kernel"], ns["tile"], ns["swapped"], ns["ksplit"]) for ns in p.all_node_stats()]
+    assert sum(x != y for x, y in zip(before, after)) == rep["nodes_changed"]
+    a1 = p.new_amps()
+    p.contract(a1)
+    torch.cuda.synchronize()
+    assert _rel(a1.cpu().numpy(), ref) <= tol
+    assert _rel(a1.cpu().numpy(), a0.cpu().numpy()) <= tol
+    batch = xeb.Batch([p])
+    batch.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(batch.amps[0], a1)
+    batch.close()
+    # String blocks (the case of test_string_blocks_match_one_block): the
+    # first block's choice reaches every block.
+    circ = grid_circuit(4, 5, 7, 641)
+    strings = uniform_bitstrings(20, 20000, 642)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=1, trials=4)
+    w = xeb.Plan(circ, strings, ch, sl, precision=precision, bind=False).stats()["workspace_bytes"]
+    pb = xeb.Plan(circ, strings, ch, sl, precision=precision, memory_budget=w // 3)
+    assert pb.stats()["n_blocks"] > 1
+    pb.autotune(reps=1)
+    ab = pb.new_amps()
+    pb.contract(ab)
+    torch.cuda.synchronize()
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    assert _rel(ab.cpu().numpy(), ref) <= tol
