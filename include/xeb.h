@@ -145,6 +145,7 @@ typedef struct {
   int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
   int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256 */
   int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
+  int32_t k_slab;            /* MFMA: complex K values staged per LDS step */
   double cmacs_per_eval;     /* |t_T| 2^(q+r) */
 } xeb_node_stats_t;
 

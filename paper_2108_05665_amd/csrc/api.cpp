@@ -182,6 +182,7 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->swapped = nb.kernel == XEB_KERNEL_MFMA ? nb.swapped : 0;
     st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : -1;
     st->ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
+    st->k_slab = nb.kernel == XEB_KERNEL_MFMA ? nb.tk : 0;
     st->cmacs_per_eval = double(st->variants) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   });
 }

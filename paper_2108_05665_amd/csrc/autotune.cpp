@@ -16,23 +16,24 @@ namespace xeb {
 namespace {
 
 struct Candidate {
-  int kernel, tile, swapped, ksplit;
+  int kernel, tile, swapped, ksplit, tk;
   bool operator==(const Candidate& o) const {
-    return kernel == o.kernel && (kernel == XEB_KERNEL_GENERIC ||
-                                  (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit));
+    return kernel == o.kernel &&
+           (kernel == XEB_KERNEL_GENERIC ||
+            (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit && tk == o.tk));
   }
 };
 
 Candidate current(const NodeBlock& nb) {
-  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, 0, 0, 1};
-  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit};
+  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, 0, 0, 1, 0};
+  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk};
 }
 
 void apply(const Node& nd, int64_t nl, int64_t nr, NodeBlock& nb, const Candidate& c) {
   if (c.kernel == XEB_KERNEL_GENERIC)
     configure_generic(nb);
   else
-    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit);
+    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk);
 }
 
 // Partial-tile bytes a split candidate needs.
@@ -49,7 +50,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   // The per-element kernel cannot win on large contractions; leave those out
   // to bound the tuning time.
-  if (useful <= std::ldexp(1.0, 30)) out.push_back({XEB_KERNEL_GENERIC, 0, 0, 1});
+  if (useful <= std::ldexp(1.0, 30)) out.push_back({XEB_KERNEL_GENERIC, 0, 0, 1, 0});
   if (!mfma_capable(nd, nl, nr, nb)) return out;
   const int64_t K = int64_t(1) << nd.kb;
   for (int sw = 0; sw < 2; ++sw) {
@@ -59,14 +60,18 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
       int bm = 0, bn = 0;
       mfma_tile_shape(tile, &bm, &bn);
       const double padded = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
-                            std::max(double(K), 16.0);
+                            std::max(double(K), double(mfma_default_slab(p->opt.precision)));
       if (16.0 * useful < padded) continue;  // mostly padding
       const int64_t tiles = node_tiles(nd, nl, nr, tile, sw);
-      for (int ks = 1; ks <= 64; ks *= 2) {
-        if (ks > 1 && (K / ks < 64 || tiles * ks > 2048)) break;
-        const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks};
-        if (partial_need(nd, nl, nr, c) > p->partial_bytes) break;
-        out.push_back(c);
+      const int lo = mfma_default_slab(p->opt.precision);
+      for (int tk = lo; tk <= 2 * lo; tk *= 2) {
+        if (!mfma_slab_allowed(tile, p->opt.precision, tk) || (tk > lo && K < tk)) continue;
+        for (int ks = 1; ks <= 64; ks *= 2) {
+          if (ks > 1 && (K / ks < 64 || tiles * ks > 2048)) break;
+          const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks, tk};
+          if (partial_need(nd, nl, nr, c) > p->partial_bytes) break;
+          out.push_back(c);
+        }
       }
     }
   }
@@ -103,7 +108,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
   const int L = p->n_leaves;
   const int nn = int(p->nodes.size());
   Block& blk0 = p->blocks.front();
-  std::vector<Candidate> chosen(nn, Candidate{XEB_KERNEL_GENERIC, 0, 0, 1});
+  std::vector<Candidate> chosen(nn, Candidate{XEB_KERNEL_GENERIC, 0, 0, 1, 0});
   for (int T = L; T < nn; ++T) {
     const Node& nd = p->nodes[T];
     NodeBlock& nb = blk0.nodes[T - L];
@@ -153,7 +158,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
       NodeBlock& nb = blk.nodes[T - L];
       const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
       Candidate c = chosen[T];
-      if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb)) c = {XEB_KERNEL_GENERIC, 0, 0, 1};
+      if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb)) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0};
       if (c.kernel == XEB_KERNEL_MFMA && partial_need(nd, nl, nr, c) > p->partial_bytes) c.ksplit = 1;
       apply(nd, nl, nr, nb, c);
     }

@@ -185,7 +185,9 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //     scaled back by 2^-(eA + eB).  LDS holds hi / lo planes [row][realified k]
 //     with (re, im) interleaved; the column operand's (re, -im) and (im, re)
 //     forms are a sign flip and a 16-bit rotation of each packed pair.
-// K is staged TK = 16 complex at a time.
+// K is staged TK complex at a time (a template parameter: 16 or 32 for
+// complex64, 32 or 64 for the split forms; larger slabs keep more bytes in
+// flight per barrier, smaller ones need fewer registers).
 //
 // The grid is persistent: each workgroup walks tiles p = blockIdx.x,
 // blockIdx.x + gridDim.x, ...; the register prefetch of the next K slab runs
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 // layout's bit positions (ubit), so each wave stores runs of consecutive
 // addresses.  With FP16 operands the epilogue also publishes the output's
 // largest magnitude for the consumer's scale.
-constexpr int TK = 16, PAD = 1, KH = 2 * TK + 8;  // KH: halves per split LDS row
+constexpr int PAD = 1;
 
 template <int CFG>
 struct Tile;
@@ -209,8 +211,10 @@ struct Tile<1> { static constexpr int BM = 32, BN = 128, MF = 32, WM = 1; };
 template <>
 struct Tile<2> { static constexpr int BM = 16, BN = 256, MF = 16, WM = 1; };
 
-template <int CFG, int PREC>
+template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
+  static constexpr int TK = TKV;
+  static constexpr int KH = 2 * TK + 8;  // halves per split LDS row
   using B_ = Tile<CFG>;
   static constexpr int BM = B_::BM, BN = B_::BN, MF = B_::MF, WM = B_::WM;
   static constexpr int WN = 4 / WM;
@@ -355,9 +359,10 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
   return amax;
 }
 
-template <int CFG, int PREC>
+template <int CFG, int PREC, int TKV>
 __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
-  using T = TileInfo<CFG, PREC>;
+  using T = TileInfo<CFG, PREC, TKV>;
+  constexpr int TK = T::TK, KH = T::KH;
   constexpr int BM = T::BM, BN = T::BN, MF = T::MF;
   typedef float accv __attribute__((ext_vector_type(T::REGS)));
   __shared__ __attribute__((aligned(16))) float smem[T::LDS];
@@ -857,7 +862,7 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
 
 namespace {
 
-template <int CFG, int PREC>
+template <int CFG, int PREC, int TKV>
 unsigned persistent_grid(int64_t tiles) {
   // Resident workgroups per device for this kernel, queried once per device.
   static int cached[64] = {};
@@ -868,7 +873,7 @@ unsigned persistent_grid(int64_t tiles) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV>, 256, 0) !=
             hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -881,12 +886,12 @@ unsigned persistent_grid(int64_t tiles) {
   return unsigned(g < 1 ? 1 : g);
 }
 
-template <int CFG, int PREC>
+template <int CFG, int PREC, int TKV>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
-  using T = TileInfo<CFG, PREC>;
+  using T = TileInfo<CFG, PREC, TKV>;
   const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
-  launch(k_contract_mfma<CFG, PREC>, dim3(persistent_grid<CFG, PREC>(tiles * a.ksplit)), dim3(256), s,
-         true, true, a);
+  launch(k_contract_mfma<CFG, PREC, TKV>, dim3(persistent_grid<CFG, PREC, TKV>(tiles * a.ksplit)), dim3(256),
+         s, true, true, a);
 }
 
 template <int CFG>
@@ -900,14 +905,24 @@ void launch_reduce_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int6
   launch(k_splitk_reduce<CFG>, dim3(unsigned(grid)), dim3(256), s, false, true, a);
 }
 
+// The (tile, precision, K slab) combinations that are instantiated.
 template <int PREC>
 void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
-  if (a.tile == 0)
-    launch_cfg<0, PREC>(a, s, rowsA, rowsB);
-  else if (a.tile == 1)
-    launch_cfg<1, PREC>(a, s, rowsA, rowsB);
-  else
-    launch_cfg<2, PREC>(a, s, rowsA, rowsB);
+  constexpr int lo = PREC == 0 ? 16 : 32, hi = 2 * lo;
+  if (a.tile == 0) {
+    if (a.tk == hi) launch_cfg<0, PREC, hi>(a, s, rowsA, rowsB);
+    else launch_cfg<0, PREC, lo>(a, s, rowsA, rowsB);
+  } else if (a.tile == 1) {
+    if constexpr (PREC == 0) {
+      if (a.tk == hi) {
+        launch_cfg<1, 0, hi>(a, s, rowsA, rowsB);
+        return;
+      }
+    }
+    launch_cfg<1, PREC, lo>(a, s, rowsA, rowsB);
+  } else {
+    launch_cfg<2, PREC, lo>(a, s, rowsA, rowsB);
+  }
 }
 
 }  // namespace
@@ -916,7 +931,8 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   const int64_t rowsA = a.nvarA << a.mb;
   const int64_t rowsB = a.nvarB << a.nb;
   if (rowsA <= 0 || rowsB <= 0) return;
-  if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * TK))))
+  if (!mfma_slab_allowed(a.tile, a.prec, a.tk)) throw std::invalid_argument("K slab not instantiated");
+  if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
   if (a.prec == 0)
     launch_prec<0>(a, s, rowsA, rowsB);
@@ -939,13 +955,25 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
     launch_reduce_cfg<2>(a, s, rowsA, rowsB);
 }
 
+bool mfma_slab_allowed(int tile, int prec, int tk) {
+  const int lo = prec == 0 ? 16 : 32;
+  if (tk == lo) return tile >= 0 && tile <= 2;
+  if (tk == 2 * lo) return tile == 0 || (prec == 0 && tile == 1);
+  return false;
+}
+
+int mfma_default_slab(int prec) { return prec == 0 ? 16 : 32; }
+
 void prepare_mfma_launch(int prec) {
   if (prec == 0) {
-    (void)persistent_grid<0, 0>(1), (void)persistent_grid<1, 0>(1), (void)persistent_grid<2, 0>(1);
+    (void)persistent_grid<0, 0, 16>(1), (void)persistent_grid<1, 0, 16>(1), (void)persistent_grid<2, 0, 16>(1);
+    (void)persistent_grid<0, 0, 32>(1), (void)persistent_grid<1, 0, 32>(1);
   } else if (prec == 1) {
-    (void)persistent_grid<0, 1>(1), (void)persistent_grid<1, 1>(1), (void)persistent_grid<2, 1>(1);
+    (void)persistent_grid<0, 1, 32>(1), (void)persistent_grid<1, 1, 32>(1), (void)persistent_grid<2, 1, 32>(1);
+    (void)persistent_grid<0, 1, 64>(1);
   } else {
-    (void)persistent_grid<0, 2>(1), (void)persistent_grid<1, 2>(1), (void)persistent_grid<2, 2>(1);
+    (void)persistent_grid<0, 2, 32>(1), (void)persistent_grid<1, 2, 32>(1), (void)persistent_grid<2, 2, 32>(1);
+    (void)persistent_grid<0, 2, 64>(1);
   }
 }
 

@@ -113,11 +113,12 @@ bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock&
 }
 
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit) {
+                    int ksplit, int tk) {
   nb.kernel = XEB_KERNEL_MFMA;
   nb.tile = tile;
   nb.swapped = swapped;
   nb.ksplit = ksplit;
+  nb.tk = tk;
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
   // Epilogue write order: tile bits sorted by the output position they feed;
@@ -152,7 +153,7 @@ int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int s
 namespace {
 
 void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, bool force_generic,
-                   int max_ksplit, double min_cmacs) {
+                   int max_ksplit, double min_cmacs, int prec) {
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   const double rowsL = double(nvarL) * std::ldexp(1.0, nd.mb);
   const double rowsR = double(nvarR) * std::ldexp(1.0, nd.nb);
@@ -163,7 +164,7 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
   const double work = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
-                      std::max(std::ldexp(1.0, nd.kb), double(16));
+                      std::max(std::ldexp(1.0, nd.kb), double(mfma_default_slab(prec)));
   // Both index forms are kept for nodes either kernel can run, so that the
   // autotuner may switch between them after compilation.
   if (mfma_capable(nd, nvarL, nvarR, nb) && nb.nvar != nvarL * nvarR) {
@@ -181,7 +182,7 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
   const int cap = max_ksplit == 0 ? 64 : max_ksplit;
   if (tiles < kSplitBelowTiles)
     while (ksplit < cap && tiles * ksplit < kSplitItems && K / (2 * ksplit) >= kMinChunk) ksplit *= 2;
-  configure_mfma(nd, nvarL, nvarR, nb, tile, swapped, ksplit);
+  configure_mfma(nd, nvarL, nvarR, nb, tile, swapped, ksplit, mfma_default_slab(prec));
 }
 
 }  // namespace
@@ -412,7 +413,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       if (!p.nodes[nd.left].leaf) std::vector<int32_t>().swap(var[nd.left]);
       if (!p.nodes[nd.right].leaf) std::vector<int32_t>().swap(var[nd.right]);
       choose_kernel(nd, nvar_of(nd.left), nr, nb, o.force_generic != 0, o.max_ksplit,
-                    o.mfma_min_cmacs > 0 ? o.mfma_min_cmacs : kMfmaMinCmacs);
+                    o.mfma_min_cmacs > 0 ? o.mfma_min_cmacs : kMfmaMinCmacs, o.precision);
     }
     for (int64_t i = 0; i < k; ++i) {
       const int64_t d = where[i];
@@ -827,6 +828,7 @@ ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
   a.pair_mode = nb.pair_mode;
   a.swapped = sw ? 1 : 0;
   a.tile = nb.tile;
+  a.tk = nb.tk;
   a.prec = p->opt.precision;
   a.mapM = bit_map(sw ? nd.maskN : nd.maskM);
   a.mapN = bit_map(sw ? nd.maskM : nd.maskN);

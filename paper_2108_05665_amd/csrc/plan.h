@@ -23,6 +23,7 @@ struct NodeBlock {
   int tile = 0;                     // MFMA tile shape (see ContractArgs::tile)
   int8_t ubit[16] = {};             // MFMA epilogue write order
   int ksplit = 1;                   // MFMA: K chunks (partial tiles + reduction)
+  int tk = 16;                      // MFMA: K slab (complex per LDS stage)
   std::vector<int32_t> pairs;       // MFMA table mode: nvarL * nvarR entries
   uint64_t off_lidx = 0, off_ridx = 0, off_pairs = 0;
 };
@@ -127,7 +128,7 @@ struct DeviceGuard {
 // autotuner's).
 bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit);
+                    int ksplit, int tk);
 void configure_generic(NodeBlock& nb);
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped);
 // Key count of node `id` in block `blk` (a leaf's: all its keys).

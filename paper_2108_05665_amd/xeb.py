@@ -105,6 +105,7 @@ class NodeStats(ctypes.Structure):
         ("swapped", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("ksplit", ctypes.c_int32),
+        ("k_slab", ctypes.c_int32),
         ("cmacs_per_eval", ctypes.c_double),
     ]
 
