@@ -146,6 +146,7 @@ typedef struct {
   int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256 */
   int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
   int32_t k_slab;            /* MFMA: complex K values staged per LDS step */
+  int32_t k_groups;          /* MFMA: groups of four waves splitting K inside a workgroup */
   double cmacs_per_eval;     /* |t_T| 2^(q+r) */
 } xeb_node_stats_t;
 
@@ -314,6 +315,29 @@ typedef struct {
   double tuning_seconds;
 } xeb_autotune_report_t;
 int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_report_t* report);
+
+/*
+ * A node's kernel configuration (as reported by xeb_plan_node_stats), for
+ * reading the autotuner's choices and applying them, or any valid
+ * configuration, to a plan with the same tree.  kernel: XEB_KERNEL_GENERIC
+ * (the other fields are ignored) or XEB_KERNEL_MFMA with tile 0..2, swapped
+ * 0/1 (right child as the row operand), ksplit a power of two with K / ksplit
+ * >= k_slab, k_slab 16 / 32 (complex64) or 32 / 64 (split forms), k_groups 1
+ * or 2 (2 and the larger slab only on some tiles).  xeb_plan_set_node_config
+ * applies it to every string block and fails with XEB_EINVAL, changing
+ * nothing, if some block cannot run it (no pair table, variant not built,
+ * split-K room exceeded).  A batch created earlier keeps its configuration.
+ */
+typedef struct {
+  int32_t kernel;
+  int32_t tile;
+  int32_t swapped;
+  int32_t ksplit;
+  int32_t k_slab;
+  int32_t k_groups;
+} xeb_node_config_t;
+int xeb_plan_get_node_config(xeb_plan_t plan, int32_t node, xeb_node_config_t* out);
+int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_config_t* config);
 
 /*
  * Batched form: several bound plans (different circuits, uneven sizes) as one

@@ -125,6 +125,24 @@ int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* 
   });
 }
 
+int xeb_plan_get_node_config(xeb_plan_t plan, int32_t node, xeb_node_config_t* out) {
+  return guarded([&] {
+    xeb::Plan& p = impl(plan);
+    if (!out) xeb::fail(XEB_EINVAL, "out is NULL");
+    if (node < p.n_leaves || node >= int32_t(p.nodes.size())) xeb::fail(XEB_EINVAL, "not an internal node");
+    *out = xeb::get_node_config(&p, node);
+  });
+}
+
+int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_config_t* config) {
+  return guarded([&] {
+    xeb::Plan& p = impl(plan);
+    if (!config) xeb::fail(XEB_EINVAL, "config is NULL");
+    if (node < p.n_leaves || node >= int32_t(p.nodes.size())) xeb::fail(XEB_EINVAL, "not an internal node");
+    xeb::set_node_config(&p, node, *config);
+  });
+}
+
 int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_report_t* report) {
   return guarded([&] {
     const xeb::AutotuneReport r =
@@ -183,6 +201,7 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : -1;
     st->ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
     st->k_slab = nb.kernel == XEB_KERNEL_MFMA ? nb.tk : 0;
+    st->k_groups = nb.kernel == XEB_KERNEL_MFMA ? nb.kg : 0;
     st->cmacs_per_eval = double(st->variants) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   });
 }

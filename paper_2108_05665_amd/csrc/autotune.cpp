@@ -16,24 +16,24 @@ namespace xeb {
 namespace {
 
 struct Candidate {
-  int kernel, tile, swapped, ksplit, tk;
+  int kernel, tile, swapped, ksplit, tk, kg;
   bool operator==(const Candidate& o) const {
-    return kernel == o.kernel &&
-           (kernel == XEB_KERNEL_GENERIC ||
-            (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit && tk == o.tk));
+    return kernel == o.kernel && (kernel == XEB_KERNEL_GENERIC ||
+                                  (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit &&
+                                   tk == o.tk && kg == o.kg));
   }
 };
 
 Candidate current(const NodeBlock& nb) {
-  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, 0, 0, 1, 0};
-  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk};
+  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
+  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk, nb.kg};
 }
 
 void apply(const Node& nd, int64_t nl, int64_t nr, NodeBlock& nb, const Candidate& c) {
   if (c.kernel == XEB_KERNEL_GENERIC)
     configure_generic(nb);
   else
-    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk);
+    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk, c.kg);
 }
 
 // Partial-tile bytes a split candidate needs.
@@ -50,7 +50,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   // The per-element kernel cannot win on large contractions; leave those out
   // to bound the tuning time.
-  if (useful <= std::ldexp(1.0, 30)) out.push_back({XEB_KERNEL_GENERIC, 0, 0, 1, 0});
+  if (useful <= std::ldexp(1.0, 30)) out.push_back({XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1});
   if (!mfma_capable(nd, nl, nr, nb)) return out;
   const int64_t K = int64_t(1) << nd.kb;
   for (int sw = 0; sw < 2; ++sw) {
@@ -64,21 +64,71 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
       if (16.0 * useful < padded) continue;  // mostly padding
       const int64_t tiles = node_tiles(nd, nl, nr, tile, sw);
       const int lo = mfma_default_slab(p->opt.precision);
-      for (int tk = lo; tk <= 2 * lo; tk *= 2) {
-        if (!mfma_slab_allowed(tile, p->opt.precision, tk) || (tk > lo && K < tk)) continue;
-        for (int ks = 1; ks <= 64; ks *= 2) {
-          if (ks > 1 && (K / ks < 64 || tiles * ks > 2048)) break;
-          const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks, tk};
-          if (partial_need(nd, nl, nr, c) > p->partial_bytes) break;
-          out.push_back(c);
+      for (int tk = lo; tk <= 2 * lo; tk *= 2)
+        for (int kg = 1; kg <= 2; ++kg) {
+          if (!mfma_variant_allowed(tile, p->opt.precision, tk, kg) || (tk > lo && K < tk) ||
+              (kg > 1 && K < 2 * tk))
+            continue;
+          for (int ks = 1; ks <= 64; ks *= 2) {
+            if (ks > 1 && (K / ks < 64 || tiles * ks > 2048)) break;
+            const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks, tk, kg};
+            if (partial_need(nd, nl, nr, c) > p->partial_bytes) break;
+            out.push_back(c);
+          }
         }
-      }
     }
   }
   return out;
 }
 
 }  // namespace
+
+xeb_node_config_t get_node_config(const Plan* p, int T) {
+  const NodeBlock& nb = p->blocks.front().nodes[T - p->n_leaves];
+  xeb_node_config_t c{};
+  c.kernel = nb.kernel;
+  if (nb.kernel == XEB_KERNEL_MFMA) {
+    c.tile = nb.tile;
+    c.swapped = nb.swapped;
+    c.ksplit = nb.ksplit;
+    c.k_slab = nb.tk;
+    c.k_groups = nb.kg;
+  } else {
+    c.ksplit = 1;
+    c.k_groups = 1;
+  }
+  return c;
+}
+
+void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
+  if (p->capturing) fail(XEB_ESTATE, "cannot change a node while a batch is being captured");
+  Candidate c{cfg.kernel, cfg.tile, cfg.swapped, cfg.ksplit, cfg.k_slab, cfg.k_groups};
+  if (c.kernel == XEB_KERNEL_GENERIC) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
+  const Node& nd = p->nodes[T];
+  const int64_t K = int64_t(1) << nd.kb;
+  if (c.kernel == XEB_KERNEL_MFMA) {
+    if (c.tile < 0 || c.tile > 2 || (c.swapped != 0 && c.swapped != 1))
+      fail(XEB_EINVAL, "invalid tile or row operand");
+    if (!mfma_variant_allowed(c.tile, p->opt.precision, c.tk, c.kg))
+      fail(XEB_EINVAL, "this K slab / K group combination is not built for the tile and precision");
+    if (c.ksplit < 1 || c.ksplit > 64 || (c.ksplit & (c.ksplit - 1)) ||
+        (c.ksplit > 1 && K % (int64_t(c.ksplit) * c.tk)))
+      fail(XEB_EINVAL, "ksplit must be a power of two leaving whole K slabs per chunk");
+  } else if (c.kernel != XEB_KERNEL_GENERIC) {
+    fail(XEB_EINVAL, "unknown kernel");
+  }
+  for (const Block& blk : p->blocks) {
+    const NodeBlock& nb = blk.nodes[T - p->n_leaves];
+    const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
+    if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb))
+      fail(XEB_EINVAL, "the node has no pair table for the MFMA kernel");
+    if (partial_need(nd, nl, nr, c) > p->partial_bytes) fail(XEB_EINVAL, "split-K room exceeded");
+  }
+  for (Block& blk : p->blocks) {
+    const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
+    apply(nd, nl, nr, blk.nodes[T - p->n_leaves], c);
+  }
+}
 
 AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
   if (!p->ws) fail(XEB_ESTATE, "no workspace bound");
@@ -108,7 +158,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
   const int L = p->n_leaves;
   const int nn = int(p->nodes.size());
   Block& blk0 = p->blocks.front();
-  std::vector<Candidate> chosen(nn, Candidate{XEB_KERNEL_GENERIC, 0, 0, 1, 0});
+  std::vector<Candidate> chosen(nn, Candidate{XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1});
   for (int T = L; T < nn; ++T) {
     const Node& nd = p->nodes[T];
     NodeBlock& nb = blk0.nodes[T - L];
@@ -158,7 +208,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
       NodeBlock& nb = blk.nodes[T - L];
       const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
       Candidate c = chosen[T];
-      if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb)) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0};
+      if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb)) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
       if (c.kernel == XEB_KERNEL_MFMA && partial_need(nd, nl, nr, c) > p->partial_bytes) c.ksplit = 1;
       apply(nd, nl, nr, nb, c);
     }

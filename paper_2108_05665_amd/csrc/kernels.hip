@@ -44,13 +44,14 @@ __device__ __forceinline__ int64_t deposit(uint64_t x, const BitMap& map) {
 // Workgroup-wide maximum of v published into the workgroup's slot (called by
 // all 256 threads).
 __device__ __forceinline__ void publish_amax(float v, unsigned long long* slots, uint32_t epoch) {
-  __shared__ float wmax[4];
+  __shared__ float wmax[8];  // up to 512 threads
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    float m = 0.f;
+    for (unsigned w = 0; w < (blockDim.x >> 6); ++w) m = fmaxf(m, wmax[w]);
     atomicMax(slots + (blockIdx.x % kAmaxSlots) * kAmaxStride,
               (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(m));
   }
@@ -359,25 +360,33 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
   return amax;
 }
 
-template <int CFG, int PREC, int TKV>
-__global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
+// KG K groups of four waves each: group g stages and multiplies the K slabs
+// g, g + KG, g + 2 KG, ... of every tile in LDS of its own (more loads in
+// flight per tile, MFMA of one group overlapping the staging of another), and
+// the groups' accumulators are summed through LDS in group order at the end
+// of the tile.
+template <int CFG, int PREC, int TKV, int KG>
+__global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   using T = TileInfo<CFG, PREC, TKV>;
   constexpr int TK = T::TK, KH = T::KH;
   constexpr int BM = T::BM, BN = T::BN, MF = T::MF;
+  constexpr int LDS_TOTAL = KG * T::LDS_MAIN > T::LDS_EPI ? KG * T::LDS_MAIN : T::LDS_EPI;
   typedef float accv __attribute__((ext_vector_type(T::REGS)));
-  __shared__ __attribute__((aligned(16))) float smem[T::LDS];
+  __shared__ __attribute__((aligned(16))) float smem[LDS_TOTAL];
   __shared__ int64_t dep_m_lo[BM];
   __shared__ int64_t dep_n_lo[BN];
-  float(*As)[2][BM + PAD] = reinterpret_cast<float(*)[2][BM + PAD]>(smem);
-  float(*Bs)[2][BN + PAD] = reinterpret_cast<float(*)[2][BN + PAD]>(smem + T::LDS_A);
+  const int grp = KG == 1 ? 0 : int(threadIdx.x >> 8);
+  float* gsmem = smem + grp * T::LDS_MAIN;
+  float(*As)[2][BM + PAD] = reinterpret_cast<float(*)[2][BM + PAD]>(gsmem);
+  float(*Bs)[2][BN + PAD] = reinterpret_cast<float(*)[2][BN + PAD]>(gsmem + T::LDS_A);
   // Split layout: hi plane then lo plane, rows of KH halves.
-  uint16_t* Ahi = reinterpret_cast<uint16_t*>(smem);
+  uint16_t* Ahi = reinterpret_cast<uint16_t*>(gsmem);
   uint16_t* Alo = Ahi + BM * KH;
-  uint16_t* Bhi = reinterpret_cast<uint16_t*>(smem + T::LDS_A);
+  uint16_t* Bhi = reinterpret_cast<uint16_t*>(gsmem + T::LDS_A);
   uint16_t* Blo = Bhi + BN * KH;
   float2* Ct = reinterpret_cast<float2*>(smem);
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & 255;  // thread within its K group
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
@@ -416,7 +425,8 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
   auto k_begin = [&](int64_t item) -> int64_t { return (item / tiles) * Kc; };
 
   float4 ra[T::A_VEC], rb[T::B_VEC];
-  auto fetch = [&](int64_t item, int64_t k0) {
+  // Loads the slab at k0 of a work item, zero beyond the item's K chunk end.
+  auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
     const int64_t tile = item % tiles;
     const int64_t row0 = (tile % tiles_m) * BM;
     const int64_t col0 = (tile / tiles_m) * BN;
@@ -425,7 +435,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
       const int e = tid + t * 256;
       const int r = e / (TK / 2), kp = e % (TK / 2);
       const int64_t gr = row0 + r, gk = k0 + 2 * kp;
-      ra[t] = (e < T::A_F4 && gr < rowsA && gk < K)
+      ra[t] = (e < T::A_F4 && gr < rowsA && gk < klim)
                   ? *reinterpret_cast<const float4*>(g.A + (gr << g.kb) + gk)
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -434,7 +444,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
       const int e = tid + t * 256;
       const int r = e / (TK / 2), kp = e % (TK / 2);
       const int64_t gr = col0 + r, gk = k0 + 2 * kp;
-      rb[t] = (e < T::B_F4 && gr < rowsB && gk < K)
+      rb[t] = (e < T::B_F4 && gr < rowsB && gk < klim)
                   ? *reinterpret_cast<const float4*>(g.B + (gr << g.kb) + gk)
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -446,7 +456,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
     if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
     return;
   }
-  fetch(item_of(p), k_begin(item_of(p)));
+  fetch(item_of(p), k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
 
   while (p < walk) {
     const int64_t item = item_of(p);
@@ -467,8 +477,8 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
           acc_im[fm][fn][v] = 0.f;
         }
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-      // Registers -> LDS.
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KG * TK) {
+      // Registers -> LDS (this group's slab k0 + grp TK).
 #pragma unroll
       for (int t = 0; t < T::A_VEC; ++t) {
         const int e = tid + t * 256;
@@ -500,10 +510,10 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
         }
       }
       __syncthreads();
-      if (k0 + TK < kend)
-        fetch(item, k0 + TK);
+      if (k0 + KG * TK < kend)
+        fetch(item, k0 + (KG + grp) * TK, kend);
       else if (pn < walk)
-        fetch(item_of(pn), k_begin(item_of(pn)));
+        fetch(item_of(pn), k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
 
       if constexpr (PREC == 0 && MF == 32) {
         const int i = lane & 31;
@@ -632,10 +642,7 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
 
     // 32x32 results: lane l, register v hold row (v % 4) + 4 (l / 32) +
     // 8 (v / 4), column l % 32.  16x16: row 4 (l / 16) + v, column l % 16.
-    if (g.ksplit > 1) {
-      // A K chunk's product goes to its partial tile, row-major (the last
-      // slab's barrier already freed LDS for the next item).
-      float2* dst = g.partial + item * (BM * BN);
+    auto for_each_result = [&](auto&& f) {
 #pragma unroll
       for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
@@ -650,30 +657,43 @@ __global__ void __launch_bounds__(256) k_contract_mfma(ContractArgs g) {
               r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
               c = wn * T::BNW + fn * 16 + (lane & 15);
             }
-            dst[r * BN + c] = make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
+            f(r, c, make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out));
           }
+    };
+    if constexpr (KG == 2) {
+      // Group 1's partial tile through LDS; group 0 adds it to its own.
+      if (grp == 1) for_each_result([&](int r, int c, float2 x) { Ct[r * (BN + 1) + c] = x; });
+      __syncthreads();
+    }
+    if (g.ksplit > 1) {
+      // A K chunk's product goes to its partial tile, row-major.
+      float2* dst = g.partial + item * (BM * BN);
+      if (grp == 0)
+        for_each_result([&](int r, int c, float2 x) {
+          if constexpr (KG == 2) {
+            const float2 y = Ct[r * (BN + 1) + c];
+            x = make_float2(x.x + y.x, x.y + y.y);
+          }
+          dst[r * BN + c] = x;
+        });
+      // (With one group the last slab's barrier already freed LDS for the
+      // next item; with two, Ct is read here.)
+      if constexpr (KG == 2) __syncthreads();
       p = pn;
       continue;
     }
     // Park the tile in LDS.
-#pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm)
-#pragma unroll
-      for (int fn = 0; fn < T::FN; ++fn)
-#pragma unroll
-        for (int v = 0; v < T::REGS; ++v) {
-          int r, c;
-          if constexpr (MF == 32) {
-            r = wm * T::BMW + fm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
-            c = wn * T::BNW + fn * 32 + (lane & 31);
-          } else {
-            r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
-            c = wn * T::BNW + fn * 16 + (lane & 15);
-          }
-          Ct[r * (BN + 1) + c] = make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
+    if (grp == 0)
+      for_each_result([&](int r, int c, float2 x) {
+        if constexpr (KG == 2) {
+          const float2 y = Ct[r * (BN + 1) + c];
+          x = make_float2(x.x + y.x, x.y + y.y);
         }
+        Ct[r * (BN + 1) + c] = x;
+      });
     __syncthreads();
-    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+    if (grp == 0)
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
   }
@@ -862,7 +882,7 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
 
 namespace {
 
-template <int CFG, int PREC, int TKV>
+template <int CFG, int PREC, int TKV, int KG>
 unsigned persistent_grid(int64_t tiles) {
   // Resident workgroups per device for this kernel, queried once per device.
   static int cached[64] = {};
@@ -873,7 +893,7 @@ unsigned persistent_grid(int64_t tiles) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV, KG>, 256 * KG, 0) !=
             hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -886,12 +906,12 @@ unsigned persistent_grid(int64_t tiles) {
   return unsigned(g < 1 ? 1 : g);
 }
 
-template <int CFG, int PREC, int TKV>
+template <int CFG, int PREC, int TKV, int KG = 1>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, PREC, TKV>;
   const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
-  launch(k_contract_mfma<CFG, PREC, TKV>, dim3(persistent_grid<CFG, PREC, TKV>(tiles * a.ksplit)), dim3(256),
-         s, true, true, a);
+  launch(k_contract_mfma<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
+         dim3(256 * KG), s, true, true, a);
 }
 
 template <int CFG>
@@ -910,8 +930,13 @@ template <int PREC>
 void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   constexpr int lo = PREC == 0 ? 16 : 32, hi = 2 * lo;
   if (a.tile == 0) {
-    if (a.tk == hi) launch_cfg<0, PREC, hi>(a, s, rowsA, rowsB);
-    else launch_cfg<0, PREC, lo>(a, s, rowsA, rowsB);
+    if (a.kg == 2) {
+      if (a.tk == hi) launch_cfg<0, PREC, hi, 2>(a, s, rowsA, rowsB);
+      else launch_cfg<0, PREC, lo, 2>(a, s, rowsA, rowsB);
+    } else {
+      if (a.tk == hi) launch_cfg<0, PREC, hi>(a, s, rowsA, rowsB);
+      else launch_cfg<0, PREC, lo>(a, s, rowsA, rowsB);
+    }
   } else if (a.tile == 1) {
     if constexpr (PREC == 0) {
       if (a.tk == hi) {
@@ -931,7 +956,8 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   const int64_t rowsA = a.nvarA << a.mb;
   const int64_t rowsB = a.nvarB << a.nb;
   if (rowsA <= 0 || rowsB <= 0) return;
-  if (!mfma_slab_allowed(a.tile, a.prec, a.tk)) throw std::invalid_argument("K slab not instantiated");
+  if (!mfma_variant_allowed(a.tile, a.prec, a.tk, a.kg))
+    throw std::invalid_argument("MFMA variant not instantiated");
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
   if (a.prec == 0)
@@ -955,7 +981,8 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
     launch_reduce_cfg<2>(a, s, rowsA, rowsB);
 }
 
-bool mfma_slab_allowed(int tile, int prec, int tk) {
+bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
+  if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
   if (tk == lo) return tile >= 0 && tile <= 2;
   if (tk == 2 * lo) return tile == 0 || (prec == 0 && tile == 1);
@@ -966,14 +993,18 @@ int mfma_default_slab(int prec) { return prec == 0 ? 16 : 32; }
 
 void prepare_mfma_launch(int prec) {
   if (prec == 0) {
-    (void)persistent_grid<0, 0, 16>(1), (void)persistent_grid<1, 0, 16>(1), (void)persistent_grid<2, 0, 16>(1);
-    (void)persistent_grid<0, 0, 32>(1), (void)persistent_grid<1, 0, 32>(1);
+    (void)persistent_grid<0, 0, 16, 1>(1), (void)persistent_grid<1, 0, 16, 1>(1);
+    (void)persistent_grid<2, 0, 16, 1>(1), (void)persistent_grid<0, 0, 32, 1>(1);
+    (void)persistent_grid<1, 0, 32, 1>(1), (void)persistent_grid<0, 0, 16, 2>(1);
+    (void)persistent_grid<0, 0, 32, 2>(1);
   } else if (prec == 1) {
-    (void)persistent_grid<0, 1, 32>(1), (void)persistent_grid<1, 1, 32>(1), (void)persistent_grid<2, 1, 32>(1);
-    (void)persistent_grid<0, 1, 64>(1);
+    (void)persistent_grid<0, 1, 32, 1>(1), (void)persistent_grid<1, 1, 32, 1>(1);
+    (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
+    (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
-    (void)persistent_grid<0, 2, 32>(1), (void)persistent_grid<1, 2, 32>(1), (void)persistent_grid<2, 2, 32>(1);
-    (void)persistent_grid<0, 2, 64>(1);
+    (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
+    (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
+    (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 

@@ -113,12 +113,13 @@ bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock&
 }
 
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit, int tk) {
+                    int ksplit, int tk, int kg) {
   nb.kernel = XEB_KERNEL_MFMA;
   nb.tile = tile;
   nb.swapped = swapped;
   nb.ksplit = ksplit;
   nb.tk = tk;
+  nb.kg = kg;
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
   // Epilogue write order: tile bits sorted by the output position they feed;
@@ -829,6 +830,7 @@ ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
   a.swapped = sw ? 1 : 0;
   a.tile = nb.tile;
   a.tk = nb.tk;
+  a.kg = nb.kg;
   a.prec = p->opt.precision;
   a.mapM = bit_map(sw ? nd.maskN : nd.maskM);
   a.mapN = bit_map(sw ? nd.maskM : nd.maskN);

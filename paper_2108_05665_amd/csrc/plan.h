@@ -24,6 +24,7 @@ struct NodeBlock {
   int8_t ubit[16] = {};             // MFMA epilogue write order
   int ksplit = 1;                   // MFMA: K chunks (partial tiles + reduction)
   int tk = 16;                      // MFMA: K slab (complex per LDS stage)
+  int kg = 1;                       // MFMA: K groups of four waves per workgroup
   std::vector<int32_t> pairs;       // MFMA table mode: nvarL * nvarR entries
   uint64_t off_lidx = 0, off_ridx = 0, off_pairs = 0;
 };
@@ -128,7 +129,7 @@ struct DeviceGuard {
 // autotuner's).
 bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit, int tk);
+                    int ksplit, int tk, int kg = 1);
 void configure_generic(NodeBlock& nb);
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped);
 // Key count of node `id` in block `blk` (a leaf's: all its keys).
@@ -146,6 +147,10 @@ struct AutotuneReport {
   double default_seconds = 0, tuned_seconds = 0, tuning_seconds = 0;
 };
 AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream);
+// A node's configuration in the first block / applied to all blocks (throws
+// XEB_EINVAL, changing nothing, if a block cannot run it).
+xeb_node_config_t get_node_config(const Plan* p, int T);
+void set_node_config(Plan* p, int T, const xeb_node_config_t& c);
 
 struct Batch;
 Batch* create_batch(Plan* const* plans, void* const* amps, int n);

@@ -106,6 +106,7 @@ class NodeStats(ctypes.Structure):
         ("tile", ctypes.c_int32),
         ("ksplit", ctypes.c_int32),
         ("k_slab", ctypes.c_int32),
+        ("k_groups", ctypes.c_int32),
         ("cmacs_per_eval", ctypes.c_double),
     ]
 
@@ -120,6 +121,17 @@ class KernelProfile(ctypes.Structure):
 
 
 KERNEL_IDS = {"generic": 0, "mfma": 1, "accumulate": 2, "splitk": 3}
+
+class NodeConfig(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("swapped", ctypes.c_int32),
+        ("ksplit", ctypes.c_int32),
+        ("k_slab", ctypes.c_int32),
+        ("k_groups", ctypes.c_int32),
+    ]
+
 
 class AutotuneReport(ctypes.Structure):
     _fields_ = [
@@ -147,6 +159,8 @@ _SIG = {
     "xeb_contract": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "xeb_fidelity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "xeb_plan_autotune": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(AutotuneReport)]),
+    "xeb_plan_get_node_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeConfig)]),
+    "xeb_plan_set_node_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeConfig)]),
     "xeb_plan_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "xeb_plan_node_stats": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeStats)]),
     "xeb_plan_set_profiling": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -321,6 +335,18 @@ class Plan:
         r = AutotuneReport()
         _check(_lib.xeb_plan_autotune(self._h, int(reps), self._stream_handle(stream), ctypes.byref(r)))
         return {name: getattr(r, name) for name, _ in AutotuneReport._fields_}
+
+    def node_config(self, node: int) -> dict:
+        c = NodeConfig()
+        _check(_lib.xeb_plan_get_node_config(self._h, int(node), ctypes.byref(c)))
+        d = {name: getattr(c, name) for name, _ in NodeConfig._fields_}
+        d["kernel"] = KERNELS.get(d["kernel"], d["kernel"])
+        return d
+
+    def set_node_config(self, node: int, kernel: str = "mfma", tile: int = 0, swapped: int = 0,
+                        ksplit: int = 1, k_slab: int = 16, k_groups: int = 1) -> None:
+        c = NodeConfig(KERNEL_IDS[kernel], tile, swapped, ksplit, k_slab, k_groups)
+        _check(_lib.xeb_plan_set_node_config(self._h, int(node), ctypes.byref(c)))
 
     def read_profile(self, kernel: str) -> dict:
         pr = KernelProfile()

@@ -225,3 +225,35 @@ def test_kernel_choice_threshold():
                 assert ns["cmacs_per_eval"] >= lim
         if thr == 65536.0:
             assert any(ns["kernel"] == "mfma" for ns in p.all_node_stats())
+
+
+def test_node_config_get_set_and_validation():
+    """Node configurations read back as set, apply to every string block,
+    and invalid ones are rejected without changing the node."""
+    c = grid_circuit(4, 5, 14, 14 * 7 + 4000)
+    s = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(c, s, n_sliced=2, trials=6)
+    p = xeb.Plan(c, s, ch, sl, bind=False, mfma_min_cmacs=65536.0)
+    mf = [ns for ns in p.all_node_stats() if ns["kernel"] == "mfma" and ns["k_bits"] >= 6]
+    assert mf
+    node = mf[0]["node"]
+    before = p.node_config(node)
+    assert before["kernel"] == "mfma" and before["k_slab"] == 16 and before["k_groups"] == 1
+    p.set_node_config(node, "mfma", tile=0, swapped=1 - before["swapped"], ksplit=1, k_slab=32, k_groups=2)
+    got = p.node_config(node)
+    assert (got["tile"], got["swapped"], got["k_slab"], got["k_groups"]) == (0, 1 - before["swapped"], 32, 2)
+    ns = {x["node"]: x for x in p.all_node_stats()}[node]
+    assert (ns["k_slab"], ns["k_groups"]) == (32, 2)
+    for bad in (dict(tile=3), dict(k_slab=64), dict(k_groups=3), dict(tile=2, k_groups=2),
+                dict(ksplit=3), dict(ksplit=1 << 7)):
+        args = dict(tile=0, swapped=0, ksplit=1, k_slab=16, k_groups=1)
+        args.update(bad)
+        with pytest.raises(xeb.XebError) as e:
+            p.set_node_config(node, "mfma", **args)
+        assert e.value.code == xeb.XEB_EINVAL
+        assert p.node_config(node) == got
+    p.set_node_config(node, "generic")
+    assert p.node_config(node)["kernel"] == "generic"
+    leaf = 0
+    with pytest.raises(xeb.XebError):
+        p.node_config(leaf)

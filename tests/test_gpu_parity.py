@@ -372,11 +372,12 @@ def test_autotune_keeps_results(precision):
     ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
     ref = statevec.state_vector(circ)[strings.astype(np.int64)]
     p, a0 = _run(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
-    before = [(ns["kernel"], ns["tile"], ns["swapped"], ns["ksplit"]) for ns in p.all_node_stats()]
+    cfg = ("kernel", "tile", "swapped", "ksplit", "k_slab", "k_groups")
+    before = [tuple(ns[f] for f in cfg) for ns in p.all_node_stats()]
     rep = p.autotune(reps=2)
     assert rep["nodes_tuned"] == len(ch) and rep["candidates"] >= len(ch)
     assert rep["tuned_seconds"] <= rep["default_seconds"]
-    after = [(ns["kernel"], ns["tile"], ns["swapped"], ns["ksplit"]) for ns in p.all_node_stats()]
+    after = [tuple(ns[f] for f in cfg) for ns in p.all_node_stats()]
     assert sum(x != y for x, y in zip(before, after)) == rep["nodes_changed"]
     a1 = p.new_amps()
     p.contract(a1)
@@ -402,3 +403,42 @@ def test_autotune_keeps_results(precision):
     torch.cuda.synchronize()
     ref = statevec.state_vector(circ)[strings.astype(np.int64)]
     assert _rel(ab.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_every_mfma_variant_vs_state_vector(precision):
+    """Every built 64x64-tile variant (K slab, one or two K groups, with and
+    without split K) forced on every MFMA-capable node: amplitudes within the
+    bound of the state vector, and reruns bit-identical."""
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
+    strings = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    lo = 16 if precision == "c64" else 32
+    p = xeb.Plan(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
+    nodes = [ns for ns in p.all_node_stats() if ns["kernel"] == "mfma"]
+    assert nodes
+    for tk in (lo, 2 * lo):
+        for kg in (1, 2):
+            for split in (False, True):
+                used = 0
+                for ns in nodes:
+                    K = 1 << ns["k_bits"]
+                    ks = 2 if split and K >= 2 * max(tk, 64) else 1
+                    if split and ks == 1:
+                        p.set_node_config(ns["node"], "mfma", tile=0, swapped=ns["swapped"],
+                                          ksplit=1, k_slab=tk, k_groups=kg)
+                        continue
+                    p.set_node_config(ns["node"], "mfma", tile=0, swapped=ns["swapped"],
+                                      ksplit=ks, k_slab=tk, k_groups=kg)
+                    used += 1
+                a = p.new_amps()
+                p.contract(a)
+                b = p.new_amps()
+                p.contract(b)
+                torch.cuda.synchronize()
+                assert torch.equal(a, b)
+                err = _rel(a.cpu().numpy(), ref)
+                assert err <= tol, (tk, kg, split, err)
+                assert used > 0
