@@ -158,8 +158,20 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the compile-time kernel choices (no per-node autotuning)")
     ap.add_argument("--autotune-reps", type=int, default=3)
+    ap.add_argument("--save-configs", metavar="PATH",
+                    help="write every node's kernel configuration (after tuning) as JSON")
+    ap.add_argument("--configs", metavar="PATH",
+                    help="apply node configurations from a --save-configs file instead of "
+                         "autotuning (the same kernels in every run, e.g. for counters)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager form only (value then comes from it)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch32"],
+                    help="the 36-qubit workload (default) or the 32-circuit batch")
+    ap.add_argument("--batch-budget-gib", type=float, default=6.0,
+                    help="batch32: HBM workspace budget per circuit")
+    ap.add_argument("--batch-max-seconds", type=float, default=2.0,
+                    help="batch32: circuits whose best plan is estimated above this many "
+                         "seconds per full contraction are planned but left out of the run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain scale kernel (read + write of this many MiB) "
                          "whose HBM counters calibrate the contraction's")
@@ -169,6 +181,9 @@ def main() -> int:
               "(slices would shard across GPUs with one all-reduce of the amplitudes)",
               file=sys.stderr)
         return 2
+
+    if args.workload == "batch32":
+        return batch_main(args)
 
     import numpy as np
     import torch
@@ -229,17 +244,26 @@ def main() -> int:
         log("oracle partials for the sampled check done")
 
     results = {}
+    saved_configs = {}
     for prec in precs:
         t0 = time.perf_counter()
         plan = xeb.Plan(circ, strings, children, sliced, device=0, precision=prec)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
         tune = None
-        if not args.no_autotune:
+        if args.configs:
+            with open(args.configs) as f:
+                for node, c in json.load(f)[prec].items():
+                    plan.set_node_config(int(node), **c)
+            log(f"{prec}: node configurations from {args.configs}")
+        elif not args.no_autotune:
             tune = plan.autotune(reps=args.autotune_reps)
             log(f"{prec}: autotuned {tune['nodes_tuned']} nodes ({tune['nodes_changed']} changed, "
                 f"{tune['candidates']} candidates) in {tune['tuning_seconds']:.1f} s; model "
                 f"{tune['default_seconds']:.3f} s -> {tune['tuned_seconds']:.3f} s per call")
+        if args.save_configs:
+            saved_configs[prec] = {ns["node"]: plan.node_config(ns["node"])
+                                   for ns in plan.all_node_stats()}
         amps = plan.new_amps()
 
         def eager_step():
@@ -308,6 +332,9 @@ def main() -> int:
         plan.close()
         del amps
 
+    if args.save_configs:
+        with open(args.save_configs, "w") as f:
+            json.dump(saved_configs, f)
     head = precs[0]
     r = results[head]
     ref_prec = "c64" if "c64" in results else None
@@ -373,6 +400,166 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(oracle_net, oracle_pairs, strings, sliced, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+BATCH_SLICINGS = (6, 8, 10, 12, 16)
+
+
+def batch_workload(i: int):
+    from synth import batch_spec, batch_circuit, uniform_bitstrings
+
+    sp = batch_spec(i)
+    circ = batch_circuit(i)
+    return sp, circ, uniform_bitstrings(circ.n_qubits, sp["k"], sp["string_seed"])
+
+
+def batch_main(args) -> int:
+    """The batch workload: 32 circuits of 30-40 qubits (rectangular grids,
+    10-14 cycles) with 10^3-10^5 uniform strings each.  Every circuit is
+    planned against a per-circuit HBM budget (tree optimizer with the table
+    memory penalty, the slice count giving the lowest estimated time that
+    compiles within the budget).  A step is the contraction of all slices of
+    all circuits and their XEB: `value` is total amplitudes / s of one
+    hipGraph launch of the whole batch; a sequential eager loop over the
+    circuits is timed beside it.  Circuits estimated above --batch-max-seconds
+    (the deep 36-40 qubit ones need minutes to hours each on one GPU) are
+    listed with their estimates and left out of the launch."""
+    import numpy as np
+
+    budget = int(args.batch_budget_gib * 2**30)
+    if args.plan_only:
+        from paper_2108_05665_amd import planner, xeb
+
+        plans = []
+        for i in range(32):
+            sp, circ, strings = batch_workload(i)
+            best = None
+            for ns in BATCH_SLICINGS:
+                ch, sl, info = planner.plan(circ, strings, n_sliced=ns, trials=8, seed=0,
+                                            anneal_steps=100000, anneal_restarts=4, workers=4,
+                                            table_bytes_max=budget)
+                try:
+                    st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
+                except xeb.XebError:
+                    continue
+                if best is None or info["seconds"] < best["info"]["seconds"]:
+                    best = {"i": i, "children": [[int(a), int(b)] for a, b in ch],
+                            "sliced": [int(x) for x in sl], "info": info,
+                            "workspace_bytes": int(st["workspace_bytes"])}
+            if best is None:
+                log(f"circuit {i}: no slicing in {BATCH_SLICINGS} fits {budget} bytes")
+                plans.append({"i": i, "included": False, "reason": "no plan within the budget"})
+                continue
+            best["included"] = best["info"]["seconds"] <= args.batch_max_seconds
+            if not best["included"]:
+                best["reason"] = "estimated above --batch-max-seconds"
+            log(f"circuit {i}: {circ.n_qubits} qubits, {sp['cycles']} cycles, k={sp['k']}, "
+                f"s={len(best['sliced'])}, estimated {best['info']['seconds']:.3f} s"
+                f"{'' if best['included'] else ' (left out)'}")
+            plans.append(best)
+        with open(args.plan_only, "w") as f:
+            json.dump({"workload": "batch32", "budget": budget,
+                       "max_seconds": args.batch_max_seconds, "plans": plans}, f)
+        return 0
+    if not args.tree:
+        print("batch32 needs --tree PATH from a --plan-only run (planning takes minutes)",
+              file=sys.stderr)
+        return 2
+    import torch
+    from paper_2108_05665_amd import xeb
+
+    with open(args.tree) as f:
+        saved = json.load(f)
+    assert saved["workload"] == "batch32"
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
+    total_k = 0
+    specs = []
+    results = {}
+    for prec in precs:
+        plans, amps = [], []
+        for rec in saved["plans"]:
+            if not rec["included"]:
+                continue
+            sp, circ, strings = batch_workload(rec["i"])
+            plan = xeb.Plan(circ, strings, rec["children"], rec["sliced"], precision=prec,
+                            memory_budget=saved["budget"])
+            if not args.no_autotune:
+                plan.autotune(reps=2)
+            plans.append(plan)
+            amps.append(plan.new_amps())
+            if prec == precs[0]:
+                total_k += len(strings)
+                specs.append({"qubits": circ.n_qubits, "cycles": sp["cycles"], "strings": sp["k"],
+                              "slices": 1 << len(rec["sliced"])})
+        log(f"{prec}: {len(plans)} plans bound, "
+            f"{sum(p.stats()['workspace_bytes'] for p in plans) / 2**30:.1f} GiB of workspace")
+
+        def eager_step():
+            for plan, a in zip(plans, amps):
+                a.zero_()
+                plan.contract(a)
+            return [plan.fidelity(a) for plan, a in zip(plans, amps)]
+
+        t0 = time.perf_counter()
+        F_eager = eager_step()
+        torch.cuda.synchronize()
+        sec_eager = time.perf_counter() - t0
+        eager_amps = [a.cpu() for a in amps]
+        log(f"{prec}: eager loop {sec_eager:.2f} s")
+        batch = xeb.Batch(plans, amps)
+        batch.launch()
+        batch.fidelities()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            batch.launch()
+            log(f"{prec}: graph step {k + 1}/{args.steps} launched")
+        F = batch.fidelities()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        same = all(torch.equal(a.cpu(), b) for a, b in zip(amps, eager_amps))
+        log(f"{prec}: graph {sec:.2f} s per batch ({total_k / sec:.0f} amplitudes/s), "
+            f"graph == eager: {same}")
+        results[prec] = dict(sec=sec, sec_eager=sec_eager, F=F, same=same,
+                             F_diff=max(abs(a - b) for a, b in zip(F, F_eager)))
+        batch.close()
+        for plan in plans:
+            plan.close()
+        del amps, eager_amps
+        torch.cuda.empty_cache()
+    head = results[precs[0]]
+    out = {
+        "metric": "amplitudes/sec (32-circuit batch, all slices, one hipGraph launch)",
+        "value": total_k / head["sec"],
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": 1e3 * head["sec"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[precs[0]],
+        "data": "synthetic",
+        "config": {"workload": "batch32: 32 circuits, 30-40 qubits on rectangular grids, 10-14 "
+                               "cycles, 10^3-10^5 uniform strings each, sliced to a per-circuit "
+                               "HBM budget; the circuits estimated above "
+                               f"{saved['max_seconds']} s per contraction left out",
+                   "strings": total_k, "budget_gib_per_circuit": saved["budget"] / 2**30,
+                   "circuits": specs,
+                   "left_out": [{"circuit": r["i"], "reason": r["reason"],
+                                 "estimated_s": r.get("info", {}).get("seconds")}
+                                for r in saved["plans"] if not r["included"]]},
+        "forms": {prec: {"amplitudes_per_s": total_k / r["sec"], "sec_per_batch": r["sec"],
+                         "eager_loop_s": r["sec_eager"],
+                         "graph_speedup_vs_eager_loop": r["sec_eager"] / r["sec"],
+                         "graph_equals_eager": r["same"], "max_xeb_diff_graph_vs_eager": r["F_diff"],
+                         "xeb": r["F"]}
+                  for prec, r in results.items()},
+    }
     print(json.dumps(out), flush=True)
     return 0
 

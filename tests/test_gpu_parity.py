@@ -442,3 +442,64 @@ def test_every_mfma_variant_vs_state_vector(precision):
                 err = _rel(a.cpu().numpy(), ref)
                 assert err <= tol, (tk, kg, split, err)
                 assert used > 0
+
+
+BATCH_PLANS = os.path.join(ROOT, "tests", "data", "batch32_plans.json")
+
+
+@pytest.mark.skipif(not os.path.exists(BATCH_PLANS), reason="batch plans not generated")
+def test_batch32_full_size():
+    """The 32-circuit batch at full size (30-40 qubits, 10^3-10^5 uniform
+    strings each, plans from bench.py --workload batch32 --plan-only; the
+    circuits that plan estimates at more than a few seconds are left out):
+    one hipGraph launch of the circuits equals the eager per-circuit runs bit
+    for bit (amplitudes and XEB); sampled per-slice partials of the three
+    smallest circuits match the oracle; every XEB is consistent with uniform
+    strings (E[F] = 0: |F| within 6 standard errors of the sample of
+    2^n |amp|^2)."""
+    from synth import batch_spec, batch_circuit
+
+    with open(BATCH_PLANS) as f:
+        saved = json.load(f)
+    assert len(saved["plans"]) == 32
+    plans, amps, work = [], [], []
+    for rec in saved["plans"]:
+        if not rec["included"]:
+            continue
+        sp = batch_spec(rec["i"])
+        circ = batch_circuit(rec["i"])
+        strings = uniform_bitstrings(circ.n_qubits, sp["k"], sp["string_seed"])
+        p = xeb.Plan(circ, strings, rec["children"], rec["sliced"], memory_budget=saved["budget"])
+        assert p.stats()["workspace_bytes"] <= saved["budget"]
+        plans.append(p)
+        amps.append(p.new_amps())
+        work.append((circ, strings, rec["sliced"]))
+    batch = xeb.Batch(plans, amps)
+    batch.launch()
+    F = batch.fidelities()
+    torch.cuda.synchronize()
+    for p, a, f, (circ, strings, _) in zip(plans, amps, F, work):
+        e = p.new_amps()
+        p.contract(e)
+        torch.cuda.synchronize()
+        assert torch.equal(a, e)
+        assert p.fidelity(e) == f
+        w = np.ldexp(np.abs(e.cpu().numpy()) ** 2, circ.n_qubits)
+        assert abs(f) <= 6.0 * w.std() / math.sqrt(len(strings)) + 1e-9, f
+        del e
+    batch.close()
+    assert len(plans) >= 8
+    smallest = sorted(range(len(plans)), key=lambda j: work[j][0].n_qubits)[:3]
+    for j in smallest:
+        circ, strings, sl = work[j]
+        sigma = (1 << len(sl)) // 3
+        part = plans[j].new_amps()
+        plans[j].contract(part, sigma, sigma + 1)
+        got = part.cpu().numpy()
+        net = build_network(circ)
+        pairs = tn.search_order(tn.closed_leg_sets(net, sl), trials=32)[0]
+        idx = [0, len(strings) // 2, len(strings) - 1]
+        ref = np.array([tn.partial_amplitude(net, int(strings[i]), sl, sigma, pairs=pairs) for i in idx])
+        assert _rel(got[idx], ref) <= AMP_TOL, j
+    for p in plans:
+        p.close()
