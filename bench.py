@@ -473,6 +473,12 @@ def batch_main(args) -> int:
     with open(args.tree) as f:
         saved = json.load(f)
     assert saved["workload"] == "batch32"
+
+    def included(rec):
+        # Every circuit with a plan within the budget, estimated at most
+        # --batch-max-seconds per contraction (the run's cap).
+        return "children" in rec and rec["info"]["seconds"] <= args.batch_max_seconds
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     total_k = 0
@@ -481,7 +487,7 @@ def batch_main(args) -> int:
     for prec in precs:
         plans, amps = [], []
         for rec in saved["plans"]:
-            if not rec["included"]:
+            if not included(rec):
                 continue
             sp, circ, strings = batch_workload(rec["i"])
             plan = xeb.Plan(circ, strings, rec["children"], rec["sliced"], precision=prec,
@@ -547,12 +553,14 @@ def batch_main(args) -> int:
         "config": {"workload": "batch32: 32 circuits, 30-40 qubits on rectangular grids, 10-14 "
                                "cycles, 10^3-10^5 uniform strings each, sliced to a per-circuit "
                                "HBM budget; the circuits estimated above "
-                               f"{saved['max_seconds']} s per contraction left out",
+                               f"{args.batch_max_seconds} s per contraction left out",
                    "strings": total_k, "budget_gib_per_circuit": saved["budget"] / 2**30,
                    "circuits": specs,
-                   "left_out": [{"circuit": r["i"], "reason": r["reason"],
-                                 "estimated_s": r.get("info", {}).get("seconds")}
-                                for r in saved["plans"] if not r["included"]]},
+                   "left_out": [{"circuit": r["i"],
+                                 "estimated_s": r.get("info", {}).get("seconds"),
+                                 "reason": "estimated above the cap" if "children" in r
+                                 else "no plan within the budget"}
+                                for r in saved["plans"] if not included(r)]},
         "forms": {prec: {"amplitudes_per_s": total_k / r["sec"], "sec_per_batch": r["sec"],
                          "eager_loop_s": r["sec_eager"],
                          "graph_speedup_vs_eager_loop": r["sec_eager"] / r["sec"],
