@@ -47,6 +47,7 @@ extern "C" {
 #define XEB_ENOMEM (-2)  /* host allocation failed, or workspace too small / over budget */
 #define XEB_EHIP (-3)    /* HIP runtime error; the message carries HIP's text */
 #define XEB_ESTATE (-4)  /* call out of order (e.g. contract before bind) */
+#define XEB_ELIMIT (-5)  /* a documented size limit exceeded (e.g. batch graph nodes) */
 
 /* Opaque plan handle. */
 typedef struct xeb_plan* xeb_plan_t;
@@ -355,8 +356,15 @@ int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_confi
  * double [n]; NaN for a plan with k = 0).
  * The plans must not be used by other calls while a launch is in flight;
  * eager calls between launches are fine.
- * Errors: XEB_EINVAL, XEB_ESTATE (a plan without workspace), XEB_EHIP.
+ * One batch graph holds at most XEB_BATCH_MAX_NODES nodes (kernel launches
+ * plus the fork / join nodes; xeb_plan_stats' evals_full is the bulk of a
+ * plan's share): a larger capture is discarded before it is instantiated
+ * and the call fails with XEB_ELIMIT.  Larger workloads are split over
+ * several batches (or run eagerly).
+ * Errors: XEB_EINVAL, XEB_ESTATE (a plan without workspace), XEB_ELIMIT,
+ * XEB_EHIP.
  */
+#define XEB_BATCH_MAX_NODES 49152
 typedef struct xeb_batch* xeb_batch_t;
 int xeb_batch_create(const xeb_plan_t* plans, void* const* amps, int32_t n, xeb_batch_t* out);
 int xeb_batch_launch(xeb_batch_t batch, void* stream);

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <limits>
 #include <set>
+#include <string>
 
 #include "plan.h"
 
@@ -16,6 +17,7 @@ struct Batch {
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int64_t nodes = 0;
   ~Batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -118,6 +120,12 @@ Batch* create_batch(Plan* const* plans, void* const* amps, int n) {
     throw;
   }
   hip_check(hipStreamEndCapture(cs, &b->graph), "hipStreamEndCapture");
+  size_t nodes = 0;
+  hip_check(hipGraphGetNodes(b->graph, nullptr, &nodes), "hipGraphGetNodes");
+  if (nodes > XEB_BATCH_MAX_NODES)
+    fail(XEB_ELIMIT, "batch graph has " + std::to_string(nodes) + " nodes, more than " +
+                         std::to_string(XEB_BATCH_MAX_NODES) + "; split the batch");
+  b->nodes = int64_t(nodes);
   hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
   return b.release();
 }

@@ -73,19 +73,101 @@ __device__ __forceinline__ int64_t extract(uint64_t x, const BitMap& map) {
 
 constexpr int kGenericLog2U = 2;  // outputs per thread in a chunk: 4
 
+// A wave-uniform int32 read through the scalar cache (the index is made
+// uniform with readfirstlane by the caller).
+__device__ __forceinline__ uint32_t load_uniform(const int32_t* p) {
+  return *(const __attribute__((address_space(4))) uint32_t*)p;
+}
+
+// Complex dot product of two rows of K = 2^kb complex (runtime K).
+__device__ __forceinline__ float2 dot_rows(const float2* pa, const float2* pb, int kb) {
+  float re = 0.f, im = 0.f;
+  if (kb >= 1) {
+    const float4* qa = reinterpret_cast<const float4*>(pa);
+    const float4* qb = reinterpret_cast<const float4*>(pb);
+    const int kv = 1 << (kb - 1);
+#pragma unroll 4
+    for (int k = 0; k < kv; ++k) {
+      const float4 x = qa[k], y = qb[k];
+      re += x.x * y.x - x.y * y.y;
+      im += x.x * y.y + x.y * y.x;
+      re += x.z * y.z - x.w * y.w;
+      im += x.z * y.w + x.w * y.z;
+    }
+  } else {
+    const float2 x = pa[0], y = pb[0];
+    re = x.x * y.x - x.y * y.y;
+    im = x.x * y.y + x.y * y.x;
+  }
+  return make_float2(re, im);
+}
+
+// Dot products of U row pairs at once, K = 2^KB complex (KB < 0: runtime
+// kb).  The loads of all U rows for a step of up to two float4 per row are
+// issued before any of them is used, so one thread keeps up to 4 U loads in
+// flight; each element sums its K terms in ascending k.
+template <int U, int KB>
+__device__ __forceinline__ void dot_rows_u(const float2* const* pa, const float2* const* pb,
+                                           int kb, float2* out) {
+  float re[U], im[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) re[u] = im[u] = 0.f;
+  if constexpr (KB == 0) {
+    float2 x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x[u] = pa[u][0];
+      y[u] = pb[u][0];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the first use
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      re[u] = x[u].x * y[u].x - x[u].y * y[u].y;
+      im[u] = x[u].x * y[u].y + x[u].y * y[u].x;
+    }
+  } else {
+    const int kv = KB > 0 ? (1 << (KB - 1)) : (1 << (kb - 1));  // float4 per row
+    constexpr int STEP = KB == 1 ? 1 : 2;
+#pragma unroll
+    for (int k = 0; k < (KB > 0 ? (1 << (KB - 1)) : kv); k += STEP) {
+      float4 x[U][STEP], y[U][STEP];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < STEP; ++j) {
+          x[u][j] = reinterpret_cast<const float4*>(pa[u])[k + j];
+          y[u][j] = reinterpret_cast<const float4*>(pb[u])[k + j];
+        }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < STEP; ++j) {
+          re[u] += x[u][j].x * y[u][j].x - x[u][j].y * y[u][j].y;
+          im[u] += x[u][j].x * y[u][j].y + x[u][j].y * y[u][j].x;
+          re[u] += x[u][j].z * y[u][j].z - x[u][j].w * y[u][j].w;
+          im[u] += x[u][j].z * y[u][j].w + x[u][j].w * y[u][j].z;
+        }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) out[u] = make_float2(re[u], im[u]);
+}
 
 // Chunks of 256 * U consecutive output elements (a key's table spans whole
 // chunks): thread t takes positions t + 256 u, u < U.  A position's row and
 // column bits split by bit range: the thread id's 8 bits (once per thread),
 // u's bits (once per thread, U values), and the chunk's high bits (once per
-// chunk, wave-uniform).  All U loads are issued before any result is used.
-template <int U, class Dot>
-__device__ __forceinline__ void generic_chunks(const ContractArgs& g, Dot& dot, float& amax) {
+// chunk, wave-uniform).  The chunk's key and its operand variants are
+// uniform (scalar loads).
+template <int U, int KB>
+__device__ __forceinline__ void generic_chunks(const ContractArgs& g, float& amax) {
   const int mn = g.mb + g.nb;
   const int64_t per = int64_t(1) << mn;
   const int64_t chunks = (g.nvar * per) / (256 * U);
-  const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
-  const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
+  const int kb = KB >= 0 ? KB : g.kb;
+  const int64_t sizeA = int64_t(1) << (g.mb + kb);
+  const int64_t sizeB = int64_t(1) << (g.nb + kb);
   const int64_t m_lo = extract(threadIdx.x, g.mapM);
   const int64_t n_lo = extract(threadIdx.x, g.mapN);
   int64_t m_u[U], n_u[U];
@@ -96,14 +178,23 @@ __device__ __forceinline__ void generic_chunks(const ContractArgs& g, Dot& dot, 
   }
   for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
     const int64_t e0 = c * (256 * U);
-    const int64_t a = e0 >> mn;
+    const int a = __builtin_amdgcn_readfirstlane(int(e0 >> mn));
+    // (Variant numbers are non-negative: zero extension.)
+    const uint32_t la = load_uniform(g.lidx + a), ra = load_uniform(g.ridx + a);
+    __builtin_amdgcn_sched_barrier(0);
     const int64_t o_hi = e0 & (per - 1);
     const int64_t m_hi = extract(o_hi, g.mapM), n_hi = extract(o_hi, g.mapN);
-    const float2* A = g.A + int64_t(g.lidx[a]) * sizeA;
-    const float2* B = g.B + int64_t(g.ridx[a]) * sizeB;
-    float2 v[U];
+    const float2* A = g.A + uint64_t(la) * sizeA;
+    const float2* B = g.B + uint64_t(ra) * sizeB;
+    const float2* pa[U];
+    const float2* pb[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = dot(A + ((m_hi | m_u[u]) << g.kb), B + ((n_hi | n_u[u]) << g.kb));
+    for (int u = 0; u < U; ++u) {
+      pa[u] = A + ((m_hi | m_u[u]) << kb);
+      pb[u] = B + ((n_hi | n_u[u]) << kb);
+    }
+    float2 v[U];
+    dot_rows_u<U, KB>(pa, pb, kb, v);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       g.C[e0 + (u << 8) + threadIdx.x] = v[u];
@@ -116,48 +207,30 @@ __device__ __forceinline__ void generic_chunks(const ContractArgs& g, Dot& dot, 
 // each finds the row m and column n its element deposits from.  Extraction is
 // linear over disjoint bit sets, so when a key's table spans at least one
 // 256-element chunk the thread id's 8 low position bits are extracted once per
-// thread and the chunk's high bits once per chunk (wave-uniform).
+// thread and the chunk's high bits once per chunk (wave-uniform).  KB is the
+// contracted dimension's bit count when it is small (the dot products unroll
+// fully), -1 otherwise.
+template <int KB>
 __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
   float amax = 0.f;
   const int mn = g.mb + g.nb;
-  const int64_t per = int64_t(1) << mn;
-  const int64_t total = g.nvar * per;
-  const int K = 1 << g.kb;
-  const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
-  const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
-  auto dot = [&](const float2* pa, const float2* pb) {
-    float re = 0.f, im = 0.f;
-    if (K >= 2) {
-      const float4* qa = reinterpret_cast<const float4*>(pa);
-      const float4* qb = reinterpret_cast<const float4*>(pb);
-#pragma unroll 4
-      for (int k = 0; k < K / 2; ++k) {
-        const float4 x = qa[k], y = qb[k];
-        re += x.x * y.x - x.y * y.y;
-        im += x.x * y.y + x.y * y.x;
-        re += x.z * y.z - x.w * y.w;
-        im += x.z * y.w + x.w * y.z;
-      }
-    } else {
-      const float2 x = pa[0], y = pb[0];
-      re = x.x * y.x - x.y * y.y;
-      im = x.x * y.y + x.y * y.x;
-    }
-    return make_float2(re, im);
-  };
   if (mn >= 8 + kGenericLog2U) {
-    generic_chunks<1 << kGenericLog2U>(g, dot, amax);
+    generic_chunks<1 << kGenericLog2U, KB>(g, amax);
   } else if (mn >= 8) {
-    generic_chunks<1>(g, dot, amax);
+    generic_chunks<1, KB>(g, amax);
   } else {
+    const int64_t per = int64_t(1) << mn;
+    const int64_t total = g.nvar * per;
+    const int64_t sizeA = int64_t(1) << (g.mb + g.kb);
+    const int64_t sizeB = int64_t(1) << (g.nb + g.kb);
     for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += int64_t(gridDim.x) * blockDim.x) {
       const int64_t a = e >> mn;
       const int64_t o = e & (per - 1);
       const int64_t m = extract(o, g.mapM);
       const int64_t n = extract(o, g.mapN);
-      const float2 v = dot(g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb),
-                           g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb));
+      const float2 v = dot_rows(g.A + int64_t(g.lidx[a]) * sizeA + (m << g.kb),
+                                g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb), g.kb);
       g.C[e] = v;
       amax = fmaxf(amax, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
@@ -215,7 +288,7 @@ struct Tile<2> { static constexpr int BM = 16, BN = 256, MF = 16, WM = 1; };
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
   static constexpr int TK = TKV;
-  static constexpr int KH = 2 * TK + 8;  // halves per split LDS row
+  static constexpr int KP = TK + 8;  // halves per split-form plane row
   using B_ = Tile<CFG>;
   static constexpr int BM = B_::BM, BN = B_::BN, MF = B_::MF, WM = B_::WM;
   static constexpr int WN = 4 / WM;
@@ -227,8 +300,9 @@ struct TileInfo {
   static constexpr int A_VEC = (A_F4 + 255) / 256;
   static constexpr int B_VEC = (B_F4 + 255) / 256;
   // LDS, in floats.
-  static constexpr int LDS_A = PREC == 0 ? TK * 2 * (BM + PAD) : BM * KH;  // (hi + lo) / 2
-  static constexpr int LDS_B = PREC == 0 ? TK * 2 * (BN + PAD) : BN * KH;
+  // (split forms: four planes of rows of KP halves)
+  static constexpr int LDS_A = PREC == 0 ? TK * 2 * (BM + PAD) : 2 * BM * KP;
+  static constexpr int LDS_B = PREC == 0 ? TK * 2 * (BN + PAD) : 2 * BN * KP;
   static constexpr int LDS_MAIN = LDS_A + LDS_B;
   static constexpr int LDS_EPI = BM * (BN + 1) * 2;
   static constexpr int LDS = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
@@ -272,25 +346,39 @@ __device__ __forceinline__ void split2(float x, uint32_t& hi, uint32_t& lo) {
   }
 }
 
-// Two complex numbers (float4) scaled by s -> packed hi and lo halves (uint2
-// each), realified order re0 im0 re1 im1.
+// Four complex numbers (x = re0 im0 re1 im1, y = re2 im2 re3 im3) scaled by s
+// -> their hi and lo halves packed per plane: re_hi, im_hi, re_lo, im_lo
+// (uint2 each, k ascending), stored at plane + row offset `at` of four planes
+// `plane` halves apart.
 template <int PREC>
-__device__ __forceinline__ void split_store(float4 v, float s, uint16_t* hi_row, uint16_t* lo_row) {
-  uint32_t h[4], l[4];
-  split2<PREC>(v.x * s, h[0], l[0]);
-  split2<PREC>(v.y * s, h[1], l[1]);
-  split2<PREC>(v.z * s, h[2], l[2]);
-  split2<PREC>(v.w * s, h[3], l[3]);
-  *reinterpret_cast<uint2*>(hi_row) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-  *reinterpret_cast<uint2*>(lo_row) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+__device__ __forceinline__ void split_store4(float4 x, float4 y, float s, uint16_t* at, int plane) {
+  uint32_t h[8], l[8];
+  split2<PREC>(x.x * s, h[0], l[0]);
+  split2<PREC>(x.y * s, h[1], l[1]);
+  split2<PREC>(x.z * s, h[2], l[2]);
+  split2<PREC>(x.w * s, h[3], l[3]);
+  split2<PREC>(y.x * s, h[4], l[4]);
+  split2<PREC>(y.y * s, h[5], l[5]);
+  split2<PREC>(y.z * s, h[6], l[6]);
+  split2<PREC>(y.w * s, h[7], l[7]);
+  *reinterpret_cast<uint2*>(at) = make_uint2(h[0] | (h[2] << 16), h[4] | (h[6] << 16));
+  *reinterpret_cast<uint2*>(at + plane) = make_uint2(h[1] | (h[3] << 16), h[5] | (h[7] << 16));
+  *reinterpret_cast<uint2*>(at + 2 * plane) = make_uint2(l[0] | (l[2] << 16), l[4] | (l[6] << 16));
+  *reinterpret_cast<uint2*>(at + 3 * plane) = make_uint2(l[1] | (l[3] << 16), l[5] | (l[7] << 16));
 }
 
-template <int MF, int PREC>
-__device__ __forceinline__ void mma16(const u32x4& a, const u32x4& b, float* acc_raw);
-
-// (re, im) pairs -> (re, -im) and (im, re).
-__device__ __forceinline__ u32x4 conj_im(u32x4 w) { return w ^ 0x80000000u; }
-__device__ __forceinline__ u32x4 swap_pair(u32x4 w) { return (w >> 16) | (w << 16); }
+// One split-form MFMA: 32x32x16 or 16x16x32, FP16 (PREC 1) or BF16 (PREC 2).
+template <int MF, int PREC, class Acc>
+__device__ __forceinline__ Acc mma_split(const u32x4& x, const u32x4& y, const Acc& acc) {
+  if constexpr (MF == 32 && PREC == 1)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0);
+  else if constexpr (MF == 32)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0);
+  else if constexpr (PREC == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0);
+}
 
 // Epilogue set-up shared by the contraction and the split-K reduction:
 // deposit tables of a tile's low row / column bits and this thread's share of
@@ -367,8 +455,9 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
 // of the tile.
 template <int CFG, int PREC, int TKV, int KG>
 __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
+  static_assert(PREC == 0, "the split forms run in k_contract_split");
   using T = TileInfo<CFG, PREC, TKV>;
-  constexpr int TK = T::TK, KH = T::KH;
+  constexpr int TK = T::TK;
   constexpr int BM = T::BM, BN = T::BN, MF = T::MF;
   constexpr int LDS_TOTAL = KG * T::LDS_MAIN > T::LDS_EPI ? KG * T::LDS_MAIN : T::LDS_EPI;
   typedef float accv __attribute__((ext_vector_type(T::REGS)));
@@ -379,11 +468,6 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   float* gsmem = smem + grp * T::LDS_MAIN;
   float(*As)[2][BM + PAD] = reinterpret_cast<float(*)[2][BM + PAD]>(gsmem);
   float(*Bs)[2][BN + PAD] = reinterpret_cast<float(*)[2][BN + PAD]>(gsmem + T::LDS_A);
-  // Split layout: hi plane then lo plane, rows of KH halves.
-  uint16_t* Ahi = reinterpret_cast<uint16_t*>(gsmem);
-  uint16_t* Alo = Ahi + BM * KH;
-  uint16_t* Bhi = reinterpret_cast<uint16_t*>(gsmem + T::LDS_A);
-  uint16_t* Blo = Bhi + BN * KH;
   float2* Ct = reinterpret_cast<float2*>(smem);
 
   const int tid = threadIdx.x & 255;  // thread within its K group
@@ -401,13 +485,6 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   const int64_t K = int64_t(1) << g.kb;
   const int64_t Kc = K / g.ksplit;
 
-  // Operand scales (FP16 split only) and the output's rescale.
-  int eA = 0, eB = 0;
-  if constexpr (PREC == 1) {
-    eA = fp16_scale_exp(g.amaxA, g.amax_nA);
-    eB = fp16_scale_exp(g.amaxB, g.amax_nB);
-  }
-  const float sA = ldexpf(1.f, eA), sB = ldexpf(1.f, eB), s_out = ldexpf(1.f, -(eA + eB));
   float amax = 0.f;
 
   int r_tid = 0, c_tid = 0;
@@ -483,30 +560,22 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       for (int t = 0; t < T::A_VEC; ++t) {
         const int e = tid + t * 256;
         if (e < T::A_F4) {
-          const int r = e / (TK / 2), kp = e % (TK / 2), kk = 2 * kp;
-          if constexpr (PREC == 0) {
-            As[kk][0][r] = ra[t].x;
-            As[kk][1][r] = ra[t].y;
-            As[kk + 1][0][r] = ra[t].z;
-            As[kk + 1][1][r] = ra[t].w;
-          } else {
-            split_store<PREC>(ra[t], sA, Ahi + r * KH + 4 * kp, Alo + r * KH + 4 * kp);
-          }
+          const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
+          As[kk][0][r] = ra[t].x;
+          As[kk][1][r] = ra[t].y;
+          As[kk + 1][0][r] = ra[t].z;
+          As[kk + 1][1][r] = ra[t].w;
         }
       }
 #pragma unroll
       for (int t = 0; t < T::B_VEC; ++t) {
         const int e = tid + t * 256;
         if (e < T::B_F4) {
-          const int r = e / (TK / 2), kp = e % (TK / 2), kk = 2 * kp;
-          if constexpr (PREC == 0) {
-            Bs[kk][0][r] = rb[t].x;
-            Bs[kk][1][r] = rb[t].y;
-            Bs[kk + 1][0][r] = rb[t].z;
-            Bs[kk + 1][1][r] = rb[t].w;
-          } else {
-            split_store<PREC>(rb[t], sB, Bhi + r * KH + 4 * kp, Blo + r * KH + 4 * kp);
-          }
+          const int r = e / (TK / 2), kk = 2 * (e % (TK / 2));
+          Bs[kk][0][r] = rb[t].x;
+          Bs[kk][1][r] = rb[t].y;
+          Bs[kk + 1][0][r] = rb[t].z;
+          Bs[kk + 1][1][r] = rb[t].w;
         }
       }
       __syncthreads();
@@ -515,7 +584,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       else if (pn < walk)
         fetch(item_of(pn), k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
 
-      if constexpr (PREC == 0 && MF == 32) {
+      if constexpr (MF == 32) {
         const int i = lane & 31;
         const int half = lane >> 5;  // 0: real part of the K = 2 pair, 1: imaginary
 #pragma unroll
@@ -540,7 +609,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
                   __builtin_amdgcn_mfma_f32_32x32x2f32(a[fm], bo_im[fn], acc_im[fm][fn], 0, 0, 0);
             }
         }
-      } else if constexpr (PREC == 0) {
+      } else {
         // 16x16x4: lane l holds k = l / 16 of the instruction's K = 4, i.e.
         // complex k (l / 32) of the pair and its part (l / 16) % 2.
         const int i = lane & 15;
@@ -569,73 +638,6 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
                   __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], bo_im[fn], acc_im[fm][fn], 0, 0, 0);
             }
         }
-      } else {
-        // Split: lane l supplies 8 consecutive realified k (4 complex) of its
-        // row / column; 32x32x16 takes lanes (row l % 32, k group l / 32) and
-        // 16x16x32 takes (row l % 16, k group l / 16).
-        constexpr int GROUPS = MF == 32 ? 2 : 4;        // k groups of 8 halves per MFMA
-        constexpr int STEPS = (2 * TK) / (8 * GROUPS);  // MFMAs along one slab
-        const int i = MF == 32 ? (lane & 31) : (lane & 15);
-        const int grp = MF == 32 ? (lane >> 5) : (lane >> 4);
-#pragma unroll
-        for (int st = 0; st < STEPS; ++st) {
-          const int ko = st * 8 * GROUPS + 8 * grp;
-          u32x4 ah[T::FM], al[T::FM];
-#pragma unroll
-          for (int fm = 0; fm < T::FM; ++fm) {
-            const int row = wm * T::BMW + fm * MF + i;
-            ah[fm] = *reinterpret_cast<const u32x4*>(Ahi + row * KH + ko);
-            al[fm] = *reinterpret_cast<const u32x4*>(Alo + row * KH + ko);
-          }
-#pragma unroll
-          for (int fn = 0; fn < T::FN; ++fn) {
-            const int col = wn * T::BNW + fn * MF + i;
-            const u32x4 bh = *reinterpret_cast<const u32x4*>(Bhi + col * KH + ko);
-            const u32x4 bl = *reinterpret_cast<const u32x4*>(Blo + col * KH + ko);
-            const u32x4 b1h = conj_im(bh), b1l = conj_im(bl);
-            const u32x4 b2h = swap_pair(bh), b2l = swap_pair(bl);
-#pragma unroll
-            for (int fm = 0; fm < T::FM; ++fm) {
-              if constexpr (MF == 32 && PREC == 1) {
-#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0)
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
-                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
-                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
-#undef XEB_MMA
-              } else if constexpr (MF == 32) {
-#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0)
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
-                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
-                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
-#undef XEB_MMA
-              } else if constexpr (PREC == 1) {
-#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, x), __builtin_bit_cast(half8, y), acc, 0, 0, 0)
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
-                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
-                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
-#undef XEB_MMA
-              } else {
-#define XEB_MMA(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0)
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1h);
-                XEB_MMA(acc_re[fm][fn], ah[fm], b1l);
-                XEB_MMA(acc_re[fm][fn], al[fm], b1h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2h);
-                XEB_MMA(acc_im[fm][fn], ah[fm], b2l);
-                XEB_MMA(acc_im[fm][fn], al[fm], b2h);
-#undef XEB_MMA
-              }
-            }
-          }
-        }
       }
       __syncthreads();
     }
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
               r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
               c = wn * T::BNW + fn * 16 + (lane & 15);
             }
-            f(r, c, make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out));
+            f(r, c, make_float2(acc_re[fm][fn][v], acc_im[fm][fn][v]));
           }
     };
     if constexpr (KG == 2) {
@@ -683,6 +685,258 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       continue;
     }
     // Park the tile in LDS.
+    if (grp == 0)
+      for_each_result([&](int r, int c, float2 x) {
+        if constexpr (KG == 2) {
+          const float2 y = Ct[r * (BN + 1) + c];
+          x = make_float2(x.x + y.x, x.y + y.y);
+        }
+        Ct[r * (BN + 1) + c] = x;
+      });
+    __syncthreads();
+    if (grp == 0)
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+    __syncthreads();
+    p = pn;
+  }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+}
+
+// Split FP16 / BF16 contraction.  Same walk, tiles, K groups, split K and
+// epilogue as k_contract_mfma; the operands are staged in LDS as four planes
+// per operand (hi re, hi im, lo re, lo im; rows of TK + 8 halves), so that
+//   re = sum ar.br - sum ai.bi,   im = sum ar.bi + sum ai.br
+// take the planes as they are: the real part keeps two accumulators (ar.br
+// and ai.bi, subtracted at the end) and no operand needs a sign flip or a
+// swap of its (re, im) halves.  Each product is hi.hi + hi.lo + lo.hi.
+// A thread stages pairs of float4 (four consecutive complex of one row), and
+// addresses inside a tile are 32-bit byte offsets from the tile's first row;
+// rows past the operand's end re-read its last row (their results are never
+// written) and only a slab that crosses the end of its K chunk is masked.
+template <int CFG, int PREC, int TKV, int KG>
+__global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
+  using T = TileInfo<CFG, PREC, TKV>;
+  constexpr int TK = T::TK, KP = T::KP;
+  constexpr int BM = T::BM, BN = T::BN, MF = T::MF;
+  constexpr int PL_A = BM * KP, PL_B = BN * KP;  // halves per plane
+  constexpr int LDS_G = T::LDS_MAIN;             // floats per K group
+  constexpr int LDS_TOTAL = KG * LDS_G > T::LDS_EPI ? KG * LDS_G : T::LDS_EPI;
+  constexpr int QR = TK / 4;                     // float4 pairs per row slab
+  constexpr int NPA = BM * QR, NPB = BN * QR;    // pairs per slab
+  constexpr int VPA = (NPA + 255) / 256, VPB = (NPB + 255) / 256;
+  typedef float accv __attribute__((ext_vector_type(T::REGS)));
+  __shared__ __attribute__((aligned(16))) float smem[LDS_TOTAL];
+  __shared__ int64_t dep_m_lo[BM];
+  __shared__ int64_t dep_n_lo[BN];
+  const int grp = KG == 1 ? 0 : int(threadIdx.x >> 8);
+  uint16_t* As = reinterpret_cast<uint16_t*>(smem + grp * LDS_G);
+  uint16_t* Bs = As + 4 * PL_A;
+  float2* Ct = reinterpret_cast<float2*>(smem);
+
+  const int tid = threadIdx.x & 255;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / T::WN, wn = wave % T::WN;
+  const int64_t rowsA = g.nvarA << g.mb;
+  const int64_t rowsB = g.nvarB << g.nb;
+  const int64_t tiles_m = (rowsA + BM - 1) / BM;
+  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  const int64_t items = tiles * g.ksplit;
+  const int64_t per_xcd = (items + 7) / 8;
+  const int64_t walk = per_xcd * 8;
+  const int64_t K = int64_t(1) << g.kb;
+  const int64_t Kc = K / g.ksplit;
+  const int row_shift = g.kb + 3;  // bytes per operand row = 2^row_shift
+
+  int eA = 0, eB = 0;
+  if constexpr (PREC == 1) {
+    eA = fp16_scale_exp(g.amaxA, g.amax_nA);
+    eB = fp16_scale_exp(g.amaxB, g.amax_nB);
+  }
+  const float sA = ldexpf(1.f, eA), sB = ldexpf(1.f, eB), s_out = ldexpf(1.f, -(eA + eB));
+  float amax = 0.f;
+
+  int r_tid = 0, c_tid = 0;
+  epilogue_setup<CFG>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
+  __syncthreads();
+
+  auto item_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
+  auto next_p = [&](int64_t p) -> int64_t {
+    for (p += gridDim.x; p < walk; p += gridDim.x)
+      if (item_of(p) < items) return p;
+    return walk;
+  };
+  auto k_begin = [&](int64_t item) -> int64_t { return (item / tiles) * Kc; };
+
+  float4 ra[VPA][2], rb[VPB][2];
+  // One operand's slab: pairs p = tid + 256 j of rows [0, BM) (row p / QR,
+  // complex 4 (p % QR) onwards).
+  auto fetch_op = [&](float4 (*rg)[2], const float2* base, int last_row, int np, int vp,
+                      bool full, int64_t k0, int64_t klim) {
+    const char* b = reinterpret_cast<const char*>(base);
+    for (int j = 0; j < vp; ++j) {
+      const int pi = tid + j * 256;
+      if (pi < np) {
+        const int r = pi / QR, q = pi % QR;
+        const int rr = r < last_row ? r : last_row;
+        const float4* src = reinterpret_cast<const float4*>(b + ((uint32_t(rr) << row_shift) + 32u * q));
+        if (full) {
+          rg[j][0] = src[0];
+          rg[j][1] = src[1];
+        } else {
+          const int64_t gk = k0 + 4 * q;
+          rg[j][0] = gk < klim ? src[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+          rg[j][1] = gk + 2 < klim ? src[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+    }
+  };
+  auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
+    const int64_t tile = item % tiles;
+    const int64_t row0 = (tile % tiles_m) * BM;
+    const int64_t col0 = (tile / tiles_m) * BN;
+    const int64_t la = rowsA - row0 - 1, lb = rowsB - col0 - 1;
+    const bool full = k0 + TK <= klim;
+    if (k0 >= klim) {
+#pragma unroll
+      for (int j = 0; j < VPA; ++j) ra[j][0] = ra[j][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < VPB; ++j) rb[j][0] = rb[j][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
+    fetch_op(ra, g.A + (row0 << g.kb) + k0, la < BM ? int(la) : BM - 1, NPA, VPA, full, k0, klim);
+    fetch_op(rb, g.B + (col0 << g.kb) + k0, lb < BN ? int(lb) : BN - 1, NPB, VPB, full, k0, klim);
+  };
+
+  int64_t p = blockIdx.x;
+  if (p < walk && item_of(p) >= items) p = next_p(p);
+  if (p >= walk) {
+    if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
+    return;
+  }
+  fetch(item_of(p), k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
+
+  constexpr int GROUPS = MF == 32 ? 2 : 4;  // lane K groups of 8 halves per MFMA
+  constexpr int KPM = 8 * GROUPS;           // K per MFMA
+  constexpr int STEPS = TK / KPM;
+  const int li = MF == 32 ? (lane & 31) : (lane & 15);
+  const int lg = MF == 32 ? (lane >> 5) : (lane >> 4);
+
+  while (p < walk) {
+    const int64_t item = item_of(p);
+    const int64_t tile = item % tiles;
+    const int64_t row0 = (tile % tiles_m) * BM;
+    const int64_t col0 = (tile / tiles_m) * BN;
+    const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
+    const int64_t pn = next_p(p);
+
+    accv acc_rr[T::FM][T::FN], acc_ii[T::FM][T::FN], acc_im[T::FM][T::FN];
+#pragma unroll
+    for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+        for (int v = 0; v < T::REGS; ++v) {
+          acc_rr[fm][fn][v] = 0.f;
+          acc_ii[fm][fn][v] = 0.f;
+          acc_im[fm][fn][v] = 0.f;
+        }
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KG * TK) {
+#pragma unroll
+      for (int j = 0; j < VPA; ++j) {
+        const int pi = tid + j * 256;
+        if (pi < NPA) split_store4<PREC>(ra[j][0], ra[j][1], sA, As + (pi / QR) * KP + 4 * (pi % QR), PL_A);
+      }
+#pragma unroll
+      for (int j = 0; j < VPB; ++j) {
+        const int pi = tid + j * 256;
+        if (pi < NPB) split_store4<PREC>(rb[j][0], rb[j][1], sB, Bs + (pi / QR) * KP + 4 * (pi % QR), PL_B);
+      }
+      __syncthreads();
+      if (k0 + KG * TK < kend)
+        fetch(item, k0 + (KG + grp) * TK, kend);
+      else if (pn < walk)
+        fetch(item_of(pn), k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
+
+#pragma unroll
+      for (int st = 0; st < STEPS; ++st) {
+        const int ko = st * KPM + 8 * lg;
+        u32x4 arh[T::FM], aih[T::FM], arl[T::FM], ail[T::FM];
+#pragma unroll
+        for (int fm = 0; fm < T::FM; ++fm) {
+          const uint16_t* a = As + (wm * T::BMW + fm * MF + li) * KP + ko;
+          arh[fm] = *reinterpret_cast<const u32x4*>(a);
+          aih[fm] = *reinterpret_cast<const u32x4*>(a + PL_A);
+          arl[fm] = *reinterpret_cast<const u32x4*>(a + 2 * PL_A);
+          ail[fm] = *reinterpret_cast<const u32x4*>(a + 3 * PL_A);
+        }
+#pragma unroll
+        for (int fn = 0; fn < T::FN; ++fn) {
+          const uint16_t* b = Bs + (wn * T::BNW + fn * MF + li) * KP + ko;
+          const u32x4 brh = *reinterpret_cast<const u32x4*>(b);
+          const u32x4 bih = *reinterpret_cast<const u32x4*>(b + PL_B);
+          const u32x4 brl = *reinterpret_cast<const u32x4*>(b + 2 * PL_B);
+          const u32x4 bil = *reinterpret_cast<const u32x4*>(b + 3 * PL_B);
+#pragma unroll
+          for (int fm = 0; fm < T::FM; ++fm) {
+#define XEB_MMA(acc, x, y) acc = mma_split<MF, PREC>(x, y, acc)
+            XEB_MMA(acc_rr[fm][fn], arh[fm], brh);
+            XEB_MMA(acc_ii[fm][fn], aih[fm], bih);
+            XEB_MMA(acc_im[fm][fn], arh[fm], bih);
+            XEB_MMA(acc_rr[fm][fn], arh[fm], brl);
+            XEB_MMA(acc_ii[fm][fn], aih[fm], bil);
+            XEB_MMA(acc_im[fm][fn], aih[fm], brh);
+            XEB_MMA(acc_rr[fm][fn], arl[fm], brh);
+            XEB_MMA(acc_ii[fm][fn], ail[fm], bih);
+            XEB_MMA(acc_im[fm][fn], arh[fm], bil);
+            XEB_MMA(acc_im[fm][fn], arl[fm], bih);
+            XEB_MMA(acc_im[fm][fn], aih[fm], brl);
+            XEB_MMA(acc_im[fm][fn], ail[fm], brh);
+#undef XEB_MMA
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    auto for_each_result = [&](auto&& f) {
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < T::FN; ++fn)
+#pragma unroll
+          for (int v = 0; v < T::REGS; ++v) {
+            int r, c;
+            if constexpr (MF == 32) {
+              r = wm * T::BMW + fm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+              c = wn * T::BNW + fn * 32 + (lane & 31);
+            } else {
+              r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
+              c = wn * T::BNW + fn * 16 + (lane & 15);
+            }
+            f(r, c, make_float2((acc_rr[fm][fn][v] - acc_ii[fm][fn][v]) * s_out,
+                                acc_im[fm][fn][v] * s_out));
+          }
+    };
+    if constexpr (KG == 2) {
+      if (grp == 1) for_each_result([&](int r, int c, float2 x) { Ct[r * (BN + 1) + c] = x; });
+      __syncthreads();
+    }
+    if (g.ksplit > 1) {
+      float2* dst = g.partial + item * (BM * BN);
+      if (grp == 0)
+        for_each_result([&](int r, int c, float2 x) {
+          if constexpr (KG == 2) {
+            const float2 y = Ct[r * (BN + 1) + c];
+            x = make_float2(x.x + y.x, x.y + y.y);
+          }
+          dst[r * BN + c] = x;
+        });
+      if constexpr (KG == 2) __syncthreads();
+      p = pn;
+      continue;
+    }
     if (grp == 0)
       for_each_result([&](int r, int c, float2 x) {
         if constexpr (KG == 2) {
@@ -877,7 +1131,14 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   int grid = grid_for(total, 256);
   if (a.mb + a.nb >= 8 + kGenericLog2U) grid = int((int64_t(grid) + (1 << kGenericLog2U) - 1) >> kGenericLog2U);
   if (a.amax_out && grid > 4096) grid = 4096;
-  launch(k_contract_generic, dim3(grid), dim3(256), s, true, true, a);
+  switch (a.kb) {
+    case 0: launch(k_contract_generic<0>, dim3(grid), dim3(256), s, true, true, a); break;
+    case 1: launch(k_contract_generic<1>, dim3(grid), dim3(256), s, true, true, a); break;
+    case 2: launch(k_contract_generic<2>, dim3(grid), dim3(256), s, true, true, a); break;
+    case 3: launch(k_contract_generic<3>, dim3(grid), dim3(256), s, true, true, a); break;
+    case 4: launch(k_contract_generic<4>, dim3(grid), dim3(256), s, true, true, a); break;
+    default: launch(k_contract_generic<-1>, dim3(grid), dim3(256), s, true, true, a); break;
+  }
 }
 
 namespace {
@@ -893,10 +1154,12 @@ unsigned persistent_grid(int64_t tiles) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV, KG>, 256 * KG, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
+    hipError_t e;
+    if constexpr (PREC == 0)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV, KG>, 256 * KG, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split<CFG, PREC, TKV, KG>, 256 * KG, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
     slot = cus * per_cu;
   }
   // The walk covers ceil(tiles / 8) * 8 positions; a multiple of 8 keeps each
@@ -910,8 +1173,12 @@ template <int CFG, int PREC, int TKV, int KG = 1>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, PREC, TKV>;
   const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
-  launch(k_contract_mfma<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
-         dim3(256 * KG), s, true, true, a);
+  if constexpr (PREC == 0)
+    launch(k_contract_mfma<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
+           dim3(256 * KG), s, true, true, a);
+  else
+    launch(k_contract_split<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
+           dim3(256 * KG), s, true, true, a);
 }
 
 template <int CFG>
@@ -958,6 +1225,7 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   if (rowsA <= 0 || rowsB <= 0) return;
   if (!mfma_variant_allowed(a.tile, a.prec, a.tk, a.kg))
     throw std::invalid_argument("MFMA variant not instantiated");
+  if (a.kb < 1 || a.kb > 21) throw std::invalid_argument("MFMA kernels take 2 <= K <= 2^21");
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
   if (a.prec == 0)

@@ -105,7 +105,9 @@ constexpr double kMfmaMinCmacs = 8388608.0;
 }  // namespace
 
 bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb) {
-  if (nd.kb < 1) return false;
+  // (K >= 2: operand rows are read as float4; K <= 2^21: in-tile byte
+  // offsets of up to 256 rows stay below 2^32.)
+  if (nd.kb < 1 || nd.kb > 21) return false;
   const double pairs = double(nvarL) * double(nvarR);
   // A sparse pair set pays for padding in the GEMM and for its table: only a
   // set with at least one key in 8 pairs can run well on MFMA.

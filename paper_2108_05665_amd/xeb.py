@@ -21,6 +21,8 @@ XEB_EINVAL = -1
 XEB_ENOMEM = -2
 XEB_EHIP = -3
 XEB_ESTATE = -4
+XEB_ELIMIT = -5
+BATCH_MAX_NODES = 49152  # nodes of one batch graph (XEB_BATCH_MAX_NODES)
 
 PRECISIONS = {"c64": 0, "split_fp16": 1, "split_bf16": 2}
 KERNELS = {0: "generic", 1: "mfma"}
@@ -372,7 +374,9 @@ class Plan:
 
 class Batch:
     """Several bound plans replayed as one hipGraph (xeb_batch_*): every launch
-    recomputes all amplitudes of all plans into `amps[i]` and their XEB."""
+    recomputes all amplitudes of all plans into `amps[i]` and their XEB.  One
+    graph holds at most BATCH_MAX_NODES nodes (XebError XEB_ELIMIT beyond;
+    BatchSet splits larger workloads)."""
 
     def __init__(self, plans, amps=None):
         self.plans = list(plans)
@@ -400,3 +404,93 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BatchSet:
+    """Plans of any total size: grouped into Batch graphs of at most
+    BATCH_MAX_NODES nodes each (greedy in list order, by the plans' launch
+    counts), and every plan too large for a graph of its own run eagerly
+    (zero, contract, XEB) after the graphs, all on one stream.  launch() and
+    fidelities() behave as Batch's."""
+
+    def __init__(self, plans, amps=None, max_nodes: int = BATCH_MAX_NODES):
+        self.plans = list(plans)
+        self.amps = list(amps) if amps is not None else [p.new_amps() for p in self.plans]
+        self.batches = []  # (Batch, indices into plans)
+        self.eager = []    # indices run eagerly
+        est = [self._estimate(p) for p in self.plans]
+        groups, cur, tot = [], [], 0
+        for i, e in enumerate(est):
+            if cur and tot + e > 0.9 * max_nodes:
+                groups.append(cur)
+                cur, tot = [], 0
+            cur.append(i)
+            tot += e
+        if cur:
+            groups.append(cur)
+        try:
+            while groups:
+                g = groups.pop(0)
+                try:
+                    self.batches.append(
+                        (Batch([self.plans[i] for i in g], [self.amps[i] for i in g]), g))
+                except XebError as err:
+                    if err.code != XEB_ELIMIT:
+                        raise
+                    if len(g) == 1:
+                        self.eager.append(g[0])
+                    else:
+                        groups[:0] = [g[:len(g) // 2], g[len(g) // 2:]]
+        except Exception:
+            self.close()
+            raise
+        self.eager.sort()
+
+    @staticmethod
+    def _estimate(p) -> int:
+        """Kernel launches of one full contraction (node evaluations, one
+        slice sum per slice and block, two split-K reductions per split
+        evaluation counted as two more launches per node evaluation)."""
+        st = p.stats()
+        extra = sum(1 for ns in p.all_node_stats() if ns["ksplit"] > 1)
+        per_slice = (1 << st["n_sliced"]) * st["n_blocks"]
+        return int(st["evals_full"]) + per_slice * (1 + 2 * extra) + 8
+
+    def launch(self, stream=None):
+        for b, _ in self.batches:
+            b.launch(stream)
+        if self.eager:
+            import torch
+
+            with torch.cuda.stream(stream) if stream is not None else _nullcontext():
+                for i in self.eager:
+                    self.amps[i].zero_()
+                    self.plans[i].contract(self.amps[i], stream=stream)
+
+    def fidelities(self, stream=None):
+        F = [float("nan")] * len(self.plans)
+        for b, g in self.batches:
+            for i, f in zip(g, b.fidelities(stream)):
+                F[i] = f
+        for i in self.eager:
+            F[i] = self.plans[i].fidelity(self.amps[i], stream=stream)
+        return F
+
+    def close(self):
+        for b, _ in self.batches:
+            b.close()
+        self.batches = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _nullcontext:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False

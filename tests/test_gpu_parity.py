@@ -452,10 +452,12 @@ def test_batch32_full_size():
     """The 32-circuit batch at full size (30-40 qubits, 10^3-10^5 uniform
     strings each, plans from bench.py --workload batch32 --plan-only; the
     circuits that plan estimates at more than a few seconds are left out):
-    one hipGraph launch of the circuits equals the eager per-circuit runs bit
-    for bit (amplitudes and XEB); sampled per-slice partials of the three
-    smallest circuits match the oracle; every XEB is consistent with uniform
-    strings (E[F] = 0: |F| within 6 standard errors of the sample of
+    the batch launched as hipGraphs of at most BATCH_MAX_NODES nodes (plans
+    too large for one graph run eagerly; their capture is refused with
+    XEB_ELIMIT before anything is instantiated) equals the eager per-circuit
+    runs bit for bit (amplitudes and XEB); sampled per-slice partials of the
+    three smallest circuits match the oracle; every XEB is consistent with
+    uniform strings (E[F] = 0: |F| within 6 standard errors of the sample of
     2^n |amp|^2)."""
     from synth import batch_spec, batch_circuit
 
@@ -474,7 +476,10 @@ def test_batch32_full_size():
         plans.append(p)
         amps.append(p.new_amps())
         work.append((circ, strings, rec["sliced"]))
-    batch = xeb.Batch(plans, amps)
+    batch = xeb.BatchSet(plans, amps)
+    covered = sorted([i for _, g in batch.batches for i in g] + batch.eager)
+    assert covered == list(range(len(plans)))
+    assert any(len(g) > 1 for _, g in batch.batches)
     batch.launch()
     F = batch.fidelities()
     torch.cuda.synchronize()
