@@ -80,11 +80,11 @@ def cpu_baseline(net, pairs, strings, sliced, budget_s: float):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", f"contract_mfma_{WORKLOAD}_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", f"contract_split_{WORKLOAD}_traffic.json")
 
 
 def measured_traffic(prec: str):
-    """HBM bytes per k_contract_mfma launch from the committed PMC summary, or
+    """HBM bytes per split-form MFMA launch from the committed PMC summary, or
     None when it covers another precision or the kernel / launch sources have
     changed since the counters were taken."""
     import hashlib
@@ -124,7 +124,7 @@ def roofline(prof: dict, prec: str) -> dict:
              "frac": gbs / HBM_PEAK_GBS}
     traffic = measured_traffic(prec)
     bytes_per_launch = mf["bytes"] / max(mf["launches"], 1)
-    r.update({"traffic": traffic, "kernel": "k_contract_mfma",
+    r.update({"traffic": traffic, "kernel": "k_contract_mfma" if prec == "c64" else "k_contract_split",
               "algorithmic_bytes_per_launch": bytes_per_launch,
               "algorithmic_flop_per_launch": flops / max(mf["launches"], 1),
               "issued_flop_per_launch": issued / max(mf["launches"], 1),
