@@ -148,6 +148,9 @@ typedef struct {
   int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
   int32_t k_slab;            /* MFMA: complex K values staged per LDS step */
   int32_t k_groups;          /* MFMA: groups of four waves splitting K inside a workgroup */
+  int32_t pair_mode;         /* MFMA key form: 0 = every (left, right) pair is a key,
+                                1 = stacked product with a pair table, 2 = keyed (one
+                                GEMM per key; the key set is too sparse to stack) */
   double cmacs_per_eval;     /* |t_T| 2^(q+r) */
 } xeb_node_stats_t;
 
@@ -324,10 +327,13 @@ int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_
  * (the other fields are ignored) or XEB_KERNEL_MFMA with tile 0..2, swapped
  * 0/1 (right child as the row operand), ksplit a power of two with K / ksplit
  * >= k_slab, k_slab 16 / 32 (complex64) or 32 / 64 (split forms), k_groups 1
- * or 2 (2 and the larger slab only on some tiles).  xeb_plan_set_node_config
- * applies it to every string block and fails with XEB_EINVAL, changing
- * nothing, if some block cannot run it (no pair table, variant not built,
- * split-K room exceeded).  A batch created earlier keeps its configuration.
+ * or 2 (2 and the larger slab only on some tiles).  A node whose key set is
+ * too sparse for the stacked product runs keyed (one GEMM per key): then
+ * each key's block must cover whole tiles and ksplit must be 1.
+ * xeb_plan_set_node_config applies it to every string block and fails with
+ * XEB_EINVAL, changing nothing, if some block cannot run it (variant not
+ * built, keyed node with keys smaller than the tile or split K, split-K
+ * room exceeded).  A batch created earlier keeps its configuration.
  */
 typedef struct {
   int32_t kernel;
@@ -336,6 +342,8 @@ typedef struct {
   int32_t ksplit;
   int32_t k_slab;
   int32_t k_groups;
+  int32_t keyed;  /* MFMA: 1 = keyed form (one GEMM per key) also where the stacked
+                     product applies; a node too sparse to stack is keyed anyway */
 } xeb_node_config_t;
 int xeb_plan_get_node_config(xeb_plan_t plan, int32_t node, xeb_node_config_t* out);
 int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_config_t* config);

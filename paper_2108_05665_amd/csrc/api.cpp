@@ -202,6 +202,7 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
     st->k_slab = nb.kernel == XEB_KERNEL_MFMA ? nb.tk : 0;
     st->k_groups = nb.kernel == XEB_KERNEL_MFMA ? nb.kg : 0;
+    st->pair_mode = nb.kernel == XEB_KERNEL_MFMA ? nb.pair_mode : 0;
     st->cmacs_per_eval = double(st->variants) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   });
 }

@@ -16,24 +16,26 @@ namespace xeb {
 namespace {
 
 struct Candidate {
-  int kernel, tile, swapped, ksplit, tk, kg;
+  int kernel, tile, swapped, ksplit, tk, kg, keyed;
   bool operator==(const Candidate& o) const {
     return kernel == o.kernel && (kernel == XEB_KERNEL_GENERIC ||
                                   (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit &&
-                                   tk == o.tk && kg == o.kg));
+                                   tk == o.tk && kg == o.kg && keyed == o.keyed));
   }
 };
 
+constexpr Candidate kGeneric{XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1, 0};
+
 Candidate current(const NodeBlock& nb) {
-  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
-  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk, nb.kg};
+  if (nb.kernel == XEB_KERNEL_GENERIC) return kGeneric;
+  return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk, nb.kg, nb.keyed};
 }
 
 void apply(const Node& nd, int64_t nl, int64_t nr, NodeBlock& nb, const Candidate& c) {
   if (c.kernel == XEB_KERNEL_GENERIC)
     configure_generic(nb);
   else
-    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk, c.kg);
+    configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk, c.kg, c.keyed);
 }
 
 // Partial-tile bytes a split candidate needs.
@@ -50,9 +52,25 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   // The per-element kernel cannot win on large contractions; leave those out
   // to bound the tuning time.
-  if (useful <= std::ldexp(1.0, 30)) out.push_back({XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1});
-  if (!mfma_capable(nd, nl, nr, nb)) return out;
+  if (useful <= std::ldexp(1.0, 30)) out.push_back(kGeneric);
   const int64_t K = int64_t(1) << nd.kb;
+  // Keyed form: the only MFMA form of a node too sparse to stack, and an
+  // alternative to the pair table (which multiplies up to 8x the useful
+  // work) where each key fills whole tiles.
+  const bool stacked = mfma_capable(nd, nl, nr, nb);
+  if (!stacked || nb.nvar != nl * nr) {
+    const int lo = mfma_default_slab(p->opt.precision);
+    for (int sw = 0; sw < 2; ++sw)
+      for (int tile = 0; tile < 3; ++tile) {
+        if (!mfma_can_run(nd, nl, nr, nb, tile, sw, 1, 1)) continue;
+        for (int tk = lo; tk <= 2 * lo; tk *= 2)
+          for (int kg = 1; kg <= 2; ++kg)
+            if (mfma_variant_allowed(tile, p->opt.precision, tk, kg) && !(tk > lo && K < tk) &&
+                !(kg > 1 && K < 2 * tk))
+              out.push_back({XEB_KERNEL_MFMA, tile, sw, 1, tk, kg, 1});
+      }
+  }
+  if (!stacked) return out;
   for (int sw = 0; sw < 2; ++sw) {
     const double rows = double(sw ? nr : nl) * std::ldexp(1.0, sw ? nd.nb : nd.mb);
     const double cols = double(sw ? nl : nr) * std::ldexp(1.0, sw ? nd.mb : nd.nb);
@@ -71,7 +89,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
             continue;
           for (int ks = 1; ks <= 64; ks *= 2) {
             if (ks > 1 && (K / ks < 64 || tiles * ks > 2048)) break;
-            const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks, tk, kg};
+            const Candidate c{XEB_KERNEL_MFMA, tile, sw, ks, tk, kg, 0};
             if (partial_need(nd, nl, nr, c) > p->partial_bytes) break;
             out.push_back(c);
           }
@@ -93,6 +111,7 @@ xeb_node_config_t get_node_config(const Plan* p, int T) {
     c.ksplit = nb.ksplit;
     c.k_slab = nb.tk;
     c.k_groups = nb.kg;
+    c.keyed = nb.pair_mode == 2 ? 1 : 0;
   } else {
     c.ksplit = 1;
     c.k_groups = 1;
@@ -102,8 +121,9 @@ xeb_node_config_t get_node_config(const Plan* p, int T) {
 
 void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
   if (p->capturing) fail(XEB_ESTATE, "cannot change a node while a batch is being captured");
-  Candidate c{cfg.kernel, cfg.tile, cfg.swapped, cfg.ksplit, cfg.k_slab, cfg.k_groups};
-  if (c.kernel == XEB_KERNEL_GENERIC) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
+  Candidate c{cfg.kernel, cfg.tile, cfg.swapped, cfg.ksplit, cfg.k_slab, cfg.k_groups, cfg.keyed};
+  if (c.kernel == XEB_KERNEL_GENERIC) c = kGeneric;
+  if (c.kernel == XEB_KERNEL_MFMA && c.keyed != 0 && c.keyed != 1) fail(XEB_EINVAL, "keyed must be 0 or 1");
   const Node& nd = p->nodes[T];
   const int64_t K = int64_t(1) << nd.kb;
   if (c.kernel == XEB_KERNEL_MFMA) {
@@ -120,8 +140,10 @@ void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
   for (const Block& blk : p->blocks) {
     const NodeBlock& nb = blk.nodes[T - p->n_leaves];
     const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
-    if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb))
-      fail(XEB_EINVAL, "the node has no pair table for the MFMA kernel");
+    if (c.kernel == XEB_KERNEL_MFMA && !mfma_can_run(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.keyed))
+      fail(XEB_EINVAL,
+           "the MFMA kernel cannot run the node so (no pair table, or keys smaller than the "
+           "tile, or split K on the keyed form)");
     if (partial_need(nd, nl, nr, c) > p->partial_bytes) fail(XEB_EINVAL, "split-K room exceeded");
   }
   for (Block& blk : p->blocks) {
@@ -158,7 +180,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
   const int L = p->n_leaves;
   const int nn = int(p->nodes.size());
   Block& blk0 = p->blocks.front();
-  std::vector<Candidate> chosen(nn, Candidate{XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1});
+  std::vector<Candidate> chosen(nn, kGeneric);
   for (int T = L; T < nn; ++T) {
     const Node& nd = p->nodes[T];
     NodeBlock& nb = blk0.nodes[T - L];
@@ -208,7 +230,8 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
       NodeBlock& nb = blk.nodes[T - L];
       const int64_t nl = nvar_in(p, blk, nd.left), nr = nvar_in(p, blk, nd.right);
       Candidate c = chosen[T];
-      if (c.kernel == XEB_KERNEL_MFMA && !mfma_capable(nd, nl, nr, nb)) c = {XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1};
+      if (c.kernel == XEB_KERNEL_MFMA && !mfma_can_run(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.keyed))
+        c = kGeneric;
       if (c.kernel == XEB_KERNEL_MFMA && partial_need(nd, nl, nr, c) > p->partial_bytes) c.ksplit = 1;
       apply(nd, nl, nr, nb, c);
     }

@@ -38,7 +38,7 @@ struct ContractArgs {
   int64_t nvar;          // T variants
   int64_t nvarA, nvarB;  // L and R variants
   int32_t mb, nb, kb;
-  int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table
+  int32_t pair_mode;     // 0: dense (a = l * nvarB + r), 1: table, 2: keyed (lidx / ridx)
   int32_t swapped;       // MFMA: rows are R's variants (A <- R, B <- L)
   int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128, 2 = 16 x 256
   int32_t tk;            // MFMA K slab (complex per LDS stage), see mfma_variant_allowed

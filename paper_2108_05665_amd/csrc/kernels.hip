@@ -380,6 +380,43 @@ __device__ __forceinline__ Acc mma_split(const u32x4& x, const u32x4& y, const A
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x), __builtin_bit_cast(bf16x8, y), acc, 0, 0, 0);
 }
 
+// Tile numbering of one launch.  Dense and table forms (pair_mode 0 / 1)
+// tile the stacked rows x stacked columns; the keyed form (pair_mode 2) tiles
+// each key's own 2^mb x 2^nb product (its operand variants from lidx / ridx,
+// swapped when A holds R), whose sides are multiples of the tile's.
+template <int BM, int BN>
+struct TileMap {
+  int64_t tiles_m = 0, per_key = 0, tiles = 0;
+  __device__ explicit TileMap(const ContractArgs& g) {
+    if (g.pair_mode == 2) {
+      tiles_m = (int64_t(1) << g.mb) / BM;
+      per_key = tiles_m * ((int64_t(1) << g.nb) / BN);
+      tiles = g.nvar * per_key;
+    } else {
+      const int64_t rowsA = g.nvarA << g.mb, rowsB = g.nvarB << g.nb;
+      tiles_m = (rowsA + BM - 1) / BM;
+      tiles = tiles_m * ((rowsB + BN - 1) / BN);
+    }
+  }
+  // First stacked row and column of `tile`, and its key (-1: not keyed).
+  __device__ void origin(const ContractArgs& g, int64_t tile, int64_t& row0, int64_t& col0,
+                         int64_t& key) const {
+    if (g.pair_mode == 2) {
+      key = tile / per_key;
+      const int64_t t = tile - key * per_key;
+      const int k32 = __builtin_amdgcn_readfirstlane(int(key));
+      const uint32_t vl = load_uniform(g.lidx + k32), vr = load_uniform(g.ridx + k32);
+      const uint32_t va = g.swapped ? vr : vl, vb = g.swapped ? vl : vr;
+      row0 = (int64_t(va) << g.mb) + (t % tiles_m) * BM;
+      col0 = (int64_t(vb) << g.nb) + (t / tiles_m) * BN;
+    } else {
+      key = -1;
+      row0 = (tile % tiles_m) * BM;
+      col0 = (tile / tiles_m) * BN;
+    }
+  }
+};
+
 // Epilogue set-up shared by the contraction and the split-K reduction:
 // deposit tables of a tile's low row / column bits and this thread's share of
 // the write order (tile element bits 0..7 come from the thread id).
@@ -410,7 +447,7 @@ __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* d
 // table in the write order ubit; returns the largest |re|, |im| written.
 template <int CFG>
 __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const float2* Ct,
-                                                int64_t row0, int64_t col0,
+                                                int64_t row0, int64_t col0, int64_t key,
                                                 const int64_t* dep_m_lo, const int64_t* dep_n_lo,
                                                 int r_tid, int c_tid) {
   using T = TileInfo<CFG, 0>;
@@ -437,10 +474,13 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
     }
     const int64_t gr = row0 + r, gc = col0 + c;
     if (gr >= rowsA || gc >= rowsB) continue;
-    const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
-    int64_t a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
-    if (g.pair_mode == 1) a = g.pairs[a];
-    if (a < 0) continue;
+    int64_t a = key;
+    if (key < 0) {
+      const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
+      a = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
+      if (g.pair_mode == 1) a = g.pairs[a];
+      if (a < 0) continue;
+    }
     const float2 val = Ct[r * (BN + 1) + c];
     g.C[a * sizeC + dep_m_hi + dep_m_lo[r] + dep_n_hi + dep_n_lo[c]] = val;
     amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
@@ -476,8 +516,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   const int wm = wave / T::WN, wn = wave % T::WN;
   const int64_t rowsA = g.nvarA << g.mb;
   const int64_t rowsB = g.nvarB << g.nb;
-  const int64_t tiles_m = (rowsA + BM - 1) / BM;
-  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  const TileMap<BM, BN> tmap(g);
+  const int64_t tiles = tmap.tiles;
   // Work items: (K chunk, tile), item = chunk * tiles + tile.
   const int64_t items = tiles * g.ksplit;
   const int64_t per_xcd = (items + 7) / 8;
@@ -504,9 +544,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   float4 ra[T::A_VEC], rb[T::B_VEC];
   // Loads the slab at k0 of a work item, zero beyond the item's K chunk end.
   auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    const int64_t tile = item % tiles;
-    const int64_t row0 = (tile % tiles_m) * BM;
-    const int64_t col0 = (tile / tiles_m) * BN;
+    int64_t row0, col0, key;
+    tmap.origin(g, item % tiles, row0, col0, key);
 #pragma unroll
     for (int t = 0; t < T::A_VEC; ++t) {
       const int e = tid + t * 256;
@@ -537,9 +576,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    const int64_t tile = item % tiles;
-    const int64_t row0 = (tile % tiles_m) * BM;
-    const int64_t col0 = (tile / tiles_m) * BN;
+    int64_t row0, col0, key;
+    tmap.origin(g, item % tiles, row0, col0, key);
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -695,7 +733,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       });
     __syncthreads();
     if (grp == 0)
-      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
   }
@@ -739,8 +777,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
   const int wm = wave / T::WN, wn = wave % T::WN;
   const int64_t rowsA = g.nvarA << g.mb;
   const int64_t rowsB = g.nvarB << g.nb;
-  const int64_t tiles_m = (rowsA + BM - 1) / BM;
-  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  const TileMap<BM, BN> tmap(g);
+  const int64_t tiles = tmap.tiles;
   const int64_t items = tiles * g.ksplit;
   const int64_t per_xcd = (items + 7) / 8;
   const int64_t walk = per_xcd * 8;
@@ -792,9 +830,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
     }
   };
   auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    const int64_t tile = item % tiles;
-    const int64_t row0 = (tile % tiles_m) * BM;
-    const int64_t col0 = (tile / tiles_m) * BN;
+    int64_t row0, col0, key;
+    tmap.origin(g, item % tiles, row0, col0, key);
     const int64_t la = rowsA - row0 - 1, lb = rowsB - col0 - 1;
     const bool full = k0 + TK <= klim;
     if (k0 >= klim) {
@@ -824,9 +861,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    const int64_t tile = item % tiles;
-    const int64_t row0 = (tile % tiles_m) * BM;
-    const int64_t col0 = (tile / tiles_m) * BN;
+    int64_t row0, col0, key;
+    tmap.origin(g, item % tiles, row0, col0, key);
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -947,7 +983,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
       });
     __syncthreads();
     if (grp == 0)
-      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
   }
@@ -986,10 +1022,8 @@ __global__ void __launch_bounds__(256) k_splitk_reduce(ContractArgs g) {
   __shared__ float2 Ct[BM * (BN + 1)];
   __shared__ int64_t dep_m_lo[BM];
   __shared__ int64_t dep_n_lo[BN];
-  const int64_t rowsA = g.nvarA << g.mb;
-  const int64_t rowsB = g.nvarB << g.nb;
-  const int64_t tiles_m = (rowsA + BM - 1) / BM;
-  const int64_t tiles = tiles_m * ((rowsB + BN - 1) / BN);
+  const TileMap<BM, BN> tmap(g);
+  const int64_t tiles = tmap.tiles;
   int r_tid = 0, c_tid = 0;
   epilogue_setup<CFG>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
   float amax = 0.f;
@@ -997,9 +1031,9 @@ __global__ void __launch_bounds__(256) k_splitk_reduce(ContractArgs g) {
     for (int e = threadIdx.x; e < BM * BN; e += 256)
       Ct[(e / BN) * (BN + 1) + (e % BN)] = g.partial[tile * (BM * BN) + e];
     __syncthreads();
-    const int64_t row0 = (tile % tiles_m) * BM;
-    const int64_t col0 = (tile / tiles_m) * BN;
-    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, dep_m_lo, dep_n_lo, r_tid, c_tid));
+    int64_t row0, col0, key;
+    tmap.origin(g, tile, row0, col0, key);
+    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
@@ -1169,10 +1203,18 @@ unsigned persistent_grid(int64_t tiles) {
   return unsigned(g < 1 ? 1 : g);
 }
 
+// Tiles of a launch (see TileMap).
+int64_t launch_tiles(const ContractArgs& a, int bm, int bn) {
+  if (a.pair_mode == 2) return a.nvar * (((int64_t(1) << a.mb) / bm) * ((int64_t(1) << a.nb) / bn));
+  const int64_t rowsA = a.nvarA << a.mb, rowsB = a.nvarB << a.nb;
+  return ((rowsA + bm - 1) / bm) * ((rowsB + bn - 1) / bn);
+}
+
 template <int CFG, int PREC, int TKV, int KG = 1>
 void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, PREC, TKV>;
-  const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
+  (void)rowsA, (void)rowsB;
+  const int64_t tiles = launch_tiles(a, T::BM, T::BN);
   if constexpr (PREC == 0)
     launch(k_contract_mfma<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
            dim3(256 * KG), s, true, true, a);
@@ -1184,7 +1226,8 @@ void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t row
 template <int CFG>
 void launch_reduce_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t rowsB) {
   using T = TileInfo<CFG, 0>;
-  const int64_t tiles = ((rowsA + T::BM - 1) / T::BM) * ((rowsB + T::BN - 1) / T::BN);
+  (void)rowsA, (void)rowsB;
+  const int64_t tiles = launch_tiles(a, T::BM, T::BN);
   const int64_t chunk_f4 = tiles * T::BM * T::BN / 2;
   launch(k_splitk_sum, dim3(grid_for(chunk_f4, 256)), dim3(256), s, true, false,
          reinterpret_cast<float4*>(a.partial), chunk_f4, a.ksplit);
@@ -1226,6 +1269,12 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   if (!mfma_variant_allowed(a.tile, a.prec, a.tk, a.kg))
     throw std::invalid_argument("MFMA variant not instantiated");
   if (a.kb < 1 || a.kb > 21) throw std::invalid_argument("MFMA kernels take 2 <= K <= 2^21");
+  if (a.pair_mode == 2) {
+    int bm = 0, bn = 0;
+    mfma_tile_shape(a.tile, &bm, &bn);
+    if (!a.lidx || !a.ridx || (int64_t(1) << a.mb) < bm || (int64_t(1) << a.nb) < bn || a.ksplit != 1)
+      throw std::invalid_argument("keyed MFMA form needs index arrays, keys of whole tiles, no split K");
+  }
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
   if (a.prec == 0)

@@ -114,8 +114,31 @@ bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock&
   return pairs <= double(1 << 26) && (nb.nvar == nvarL * nvarR || pairs <= 8.0 * double(nb.nvar));
 }
 
+bool mfma_keyed_fits(const Node& nd, int tile, int swapped) {
+  int bm = 0, bn = 0;
+  mfma_tile_shape(tile, &bm, &bn);
+  const int rb = swapped ? nd.nb : nd.mb, cb = swapped ? nd.mb : nd.nb;
+  return (int64_t(1) << rb) >= bm && (int64_t(1) << cb) >= bn;
+}
+
+bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb) {
+  if (nd.kb < 1 || nd.kb > 21 || mfma_capable(nd, nvarL, nvarR, nb)) return false;
+  for (int tile = 0; tile < 3; ++tile)
+    for (int sw = 0; sw < 2; ++sw)
+      if (mfma_keyed_fits(nd, tile, sw)) return true;
+  return false;
+}
+
+bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
+                  int swapped, int ksplit, int keyed) {
+  const bool stacked = mfma_capable(nd, nvarL, nvarR, nb);
+  if (stacked && !keyed) return true;
+  return ksplit == 1 && nd.kb >= 1 && nd.kb <= 21 && mfma_keyed_fits(nd, tile, swapped) &&
+         (stacked || mfma_keyed(nd, nvarL, nvarR, nb));
+}
+
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit, int tk, int kg) {
+                    int ksplit, int tk, int kg, int want_keyed) {
   nb.kernel = XEB_KERNEL_MFMA;
   nb.tile = tile;
   nb.swapped = swapped;
@@ -135,12 +158,13 @@ void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb,
   std::sort(keyed.begin(), keyed.end());
   std::memset(nb.ubit, 0, sizeof(nb.ubit));
   for (size_t b = 0; b < keyed.size(); ++b) nb.ubit[b] = int8_t(keyed[b].second);
-  nb.pair_mode = (nb.nvar == nvarL * nvarR) ? 0 : 1;
-  (void)nvarR;
+  nb.pair_mode = (want_keyed || !mfma_capable(nd, nvarL, nvarR, nb)) ? 2 : (nb.nvar == nvarL * nvarR ? 0 : 1);
+  nb.keyed = nb.pair_mode == 2 ? 1 : 0;
 }
 
 void configure_generic(NodeBlock& nb) {
   nb.kernel = XEB_KERNEL_GENERIC;
+  nb.keyed = 0;
   nb.tile = 0;
   nb.swapped = 0;
   nb.ksplit = 1;
@@ -148,6 +172,7 @@ void configure_generic(NodeBlock& nb) {
 }
 
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped) {
+  // (Stacked form; the keyed form never splits K.)
   int64_t rows = nvarL << nd.mb, cols = nvarR << nd.nb;
   if (swapped) std::swap(rows, cols);
   return mfma_tiles(tile, rows, cols);
@@ -176,8 +201,23 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
       nb.pairs[size_t(int64_t(nb.lidx[v]) * nvarR + nb.ridx[v])] = int32_t(v);
   }
   configure_generic(nb);
-  if (force_generic || !mfma_capable(nd, nvarL, nvarR, nb) || rows < 8 || cols < 64 ||
-      useful < min_cmacs || 8 * useful < work)
+  if (force_generic) return;
+  if (mfma_keyed(nd, nvarL, nvarR, nb)) {
+    // One GEMM per key: the largest tile that each key's block fills, the
+    // unswapped orientation first.
+    const double keyed_work = useful / std::ldexp(1.0, nd.kb) *
+                              std::max(std::ldexp(1.0, nd.kb), double(mfma_default_slab(prec)));
+    if (useful < min_cmacs || 8 * useful < keyed_work) return;
+    for (int t = 0; t < 3; ++t)
+      for (int sw = 0; sw < 2; ++sw)
+        if (mfma_keyed_fits(nd, t, sw)) {
+          configure_mfma(nd, nvarL, nvarR, nb, t, sw, 1, mfma_default_slab(prec));
+          return;
+        }
+    return;
+  }
+  if (!mfma_capable(nd, nvarL, nvarR, nb) || rows < 8 || cols < 64 || useful < min_cmacs ||
+      8 * useful < work)
     return;
   int ksplit = 1;
   const int64_t tiles = mfma_tiles(tile, int64_t(rows), int64_t(cols));

@@ -18,7 +18,8 @@ struct NodeBlock {
   int64_t nvar = 1;                 // distinct keys of the node in this block
   std::vector<int32_t> lidx, ridx;  // child keys of each key (generic kernel)
   int kernel = XEB_KERNEL_GENERIC;
-  int pair_mode = 0;                // MFMA: 0 dense, 1 table
+  int pair_mode = 0;                // MFMA: 0 dense, 1 table, 2 keyed (one GEMM per key)
+  int keyed = 0;                    // MFMA: keyed form requested where stacking applies
   int swapped = 0;                  // MFMA: right child supplies the tile rows
   int tile = 0;                     // MFMA tile shape (see ContractArgs::tile)
   int8_t ubit[16] = {};             // MFMA epilogue write order
@@ -127,9 +128,19 @@ struct DeviceGuard {
 
 // Kernel configuration of one node in one block (compile-time choice or the
 // autotuner's).
+// Stacked MFMA form (all key pairs, or a pair table): the node's key set is
+// dense enough.
 bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
+// Keyed MFMA form (one GEMM per key): the stacked form does not apply and
+// each key's 2^mb x 2^nb product covers whole tiles of `tile` with the given
+// row operand.
+bool mfma_keyed_fits(const Node& nd, int tile, int swapped);
+bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
+// Whether the MFMA kernel can run the node in this configuration.
+bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
+                  int swapped, int ksplit, int keyed = 0);
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
-                    int ksplit, int tk, int kg = 1);
+                    int ksplit, int tk, int kg = 1, int keyed = 0);
 void configure_generic(NodeBlock& nb);
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped);
 // Key count of node `id` in block `blk` (a leaf's: all its keys).

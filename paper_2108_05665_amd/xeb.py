@@ -109,6 +109,7 @@ class NodeStats(ctypes.Structure):
         ("ksplit", ctypes.c_int32),
         ("k_slab", ctypes.c_int32),
         ("k_groups", ctypes.c_int32),
+        ("pair_mode", ctypes.c_int32),
         ("cmacs_per_eval", ctypes.c_double),
     ]
 
@@ -132,6 +133,7 @@ class NodeConfig(ctypes.Structure):
         ("ksplit", ctypes.c_int32),
         ("k_slab", ctypes.c_int32),
         ("k_groups", ctypes.c_int32),
+        ("keyed", ctypes.c_int32),
     ]
 
 
@@ -346,8 +348,8 @@ class Plan:
         return d
 
     def set_node_config(self, node: int, kernel: str = "mfma", tile: int = 0, swapped: int = 0,
-                        ksplit: int = 1, k_slab: int = 16, k_groups: int = 1) -> None:
-        c = NodeConfig(KERNEL_IDS[kernel], tile, swapped, ksplit, k_slab, k_groups)
+                        ksplit: int = 1, k_slab: int = 16, k_groups: int = 1, keyed: int = 0) -> None:
+        c = NodeConfig(KERNEL_IDS[kernel], tile, swapped, ksplit, k_slab, k_groups, keyed)
         _check(_lib.xeb_plan_set_node_config(self._h, int(node), ctypes.byref(c)))
 
     def read_profile(self, kernel: str) -> dict:

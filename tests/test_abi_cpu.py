@@ -252,6 +252,27 @@ def test_node_config_get_set_and_validation():
             p.set_node_config(node, "mfma", **args)
         assert e.value.code == xeb.XEB_EINVAL
         assert p.node_config(node) == got
+    # Keyed form (one GEMM per key): needs keys that fill the tile and no split K.
+    big = [ns for ns in p.all_node_stats() if 1 <= ns["k_bits"] <= 21 and ns["m_bits"] >= 6
+           and ns["n_bits"] >= 6]
+    if big:
+        kn = big[0]["node"]
+        p.set_node_config(kn, "mfma", tile=0, swapped=0, ksplit=1, k_slab=16, k_groups=1, keyed=1)
+        assert p.node_config(kn)["keyed"] == 1
+        assert {x["node"]: x for x in p.all_node_stats()}[kn]["pair_mode"] == 2
+        with pytest.raises(xeb.XebError) as e:
+            p.set_node_config(kn, "mfma", tile=0, swapped=0, ksplit=2, k_slab=16, k_groups=1, keyed=1)
+        assert e.value.code == xeb.XEB_EINVAL
+        p.set_node_config(kn, "mfma", tile=0, swapped=0, ksplit=1, k_slab=16, k_groups=1, keyed=0)
+        assert p.node_config(kn)["keyed"] == 0
+    small = [ns for ns in p.all_node_stats() if 1 <= ns["k_bits"] <= 21 and ns["m_bits"] < 4
+             and ns["n_bits"] < 4]
+    if small:
+        with pytest.raises(xeb.XebError) as e:
+            p.set_node_config(small[0]["node"], "mfma", tile=0, swapped=0, ksplit=1, k_slab=16,
+                              k_groups=1, keyed=1)
+        assert e.value.code == xeb.XEB_EINVAL
+    assert big or small
     p.set_node_config(node, "generic")
     assert p.node_config(node)["kernel"] == "generic"
     leaf = 0

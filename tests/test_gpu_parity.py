@@ -444,6 +444,46 @@ def test_every_mfma_variant_vs_state_vector(precision):
                 assert used > 0
 
 
+@pytest.mark.parametrize("precision", ["c64", "split_fp16"])
+def test_keyed_form_vs_state_vector(precision):
+    """The keyed MFMA form (one GEMM per key, operand variants from the key's
+    index pair) forced on every node whose keys fill a tile: amplitudes within
+    the bound of the state vector, reruns bit-identical, and every forced node
+    reports the keyed form."""
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
+    strings = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    slab = 16 if precision == "c64" else 32
+    p = xeb.Plan(circ, strings, ch, sl, precision=precision, **SMALL_MFMA)
+    forced = []
+    for ns in p.all_node_stats():
+        if not 1 <= ns["k_bits"] <= 21:
+            continue
+        for tile, bm, bn in ((0, 64, 64), (1, 32, 128), (2, 16, 256)):
+            for sw in (0, 1):
+                rows, cols = (ns["n_bits"], ns["m_bits"]) if sw else (ns["m_bits"], ns["n_bits"])
+                if (1 << rows) >= bm and (1 << cols) >= bn:
+                    break
+            else:
+                continue
+            p.set_node_config(ns["node"], "mfma", tile=tile, swapped=sw, ksplit=1, k_slab=slab,
+                              k_groups=1, keyed=1)
+            forced.append(ns["node"])
+            break
+    assert len(forced) >= 3
+    by_node = {ns["node"]: ns for ns in p.all_node_stats()}
+    assert all(by_node[t]["pair_mode"] == 2 and p.node_config(t)["keyed"] == 1 for t in forced)
+    a = p.new_amps()
+    p.contract(a)
+    b = p.new_amps()
+    p.contract(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert _rel(a.cpu().numpy(), ref) <= tol
+
+
 BATCH_PLANS = os.path.join(ROOT, "tests", "data", "batch32_plans.json")
 
 
