@@ -61,7 +61,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   if (!stacked || nb.nvar != nl * nr) {
     const int lo = mfma_default_slab(p->opt.precision);
     for (int sw = 0; sw < 2; ++sw)
-      for (int tile = 0; tile < 3; ++tile) {
+      for (int tile = 0; tile < kMfmaTiles; ++tile) {
         if (!mfma_can_run(nd, nl, nr, nb, tile, sw, 1, 1)) continue;
         for (int tk = lo; tk <= 2 * lo; tk *= 2)
           for (int kg = 1; kg <= 2; ++kg)
@@ -74,7 +74,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   for (int sw = 0; sw < 2; ++sw) {
     const double rows = double(sw ? nr : nl) * std::ldexp(1.0, sw ? nd.nb : nd.mb);
     const double cols = double(sw ? nl : nr) * std::ldexp(1.0, sw ? nd.mb : nd.nb);
-    for (int tile = 0; tile < 3; ++tile) {
+    for (int tile = 0; tile < kMfmaTiles; ++tile) {
       int bm = 0, bn = 0;
       mfma_tile_shape(tile, &bm, &bn);
       const double padded = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
@@ -127,7 +127,7 @@ void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
   const Node& nd = p->nodes[T];
   const int64_t K = int64_t(1) << nd.kb;
   if (c.kernel == XEB_KERNEL_MFMA) {
-    if (c.tile < 0 || c.tile > 2 || (c.swapped != 0 && c.swapped != 1))
+    if (c.tile < 0 || c.tile >= kMfmaTiles || (c.swapped != 0 && c.swapped != 1))
       fail(XEB_EINVAL, "invalid tile or row operand");
     if (!mfma_variant_allowed(c.tile, p->opt.precision, c.tk, c.kg))
       fail(XEB_EINVAL, "this K slab / K group combination is not built for the tile and precision");

@@ -86,6 +86,7 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 // them and writes T.
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
 void launch_splitk_reduce(const ContractArgs& a, hipStream_t s);
+constexpr int kMfmaTiles = 4;  // tile shapes 0..3 (see mfma_tile_shape)
 void mfma_tile_shape(int tile, int* bm, int* bn);
 // MFMA variants that are built: K slab complex64 16 (all tiles) or 32
 // (64 x 64, 32 x 128), split forms 32 (all tiles) or 64 (64 x 64); two K

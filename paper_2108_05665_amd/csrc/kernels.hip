@@ -246,6 +246,7 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //   0: 64 x 64,  waves 2 x 2, one 32 x 32 block each
 //   1: 32 x 128, waves 1 x 4, one 32 x 32 block each
 //   2: 16 x 256, waves 1 x 4, four 16 x 16 blocks each
+//   3: 64 x 16,  waves 4 x 1, one 16 x 16 block each (narrow keyed products)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -284,6 +285,8 @@ template <>
 struct Tile<1> { static constexpr int BM = 32, BN = 128, MF = 32, WM = 1; };
 template <>
 struct Tile<2> { static constexpr int BM = 16, BN = 256, MF = 16, WM = 1; };
+template <>
+struct Tile<3> { static constexpr int BM = 64, BN = 16, MF = 16, WM = 4; };
 
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
@@ -307,7 +310,7 @@ struct TileInfo {
   static constexpr int LDS_EPI = BM * (BN + 1) * 2;
   static constexpr int LDS = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
   static constexpr int LOG_BM = BM == 64 ? 6 : (BM == 32 ? 5 : 4);
-  static constexpr int LOG_BN = BN == 64 ? 6 : (BN == 128 ? 7 : 8);
+  static constexpr int LOG_BN = BN == 16 ? 4 : (BN == 64 ? 6 : (BN == 128 ? 7 : 8));
   static constexpr int UBITS = LOG_BM + LOG_BN;
   static constexpr int PER_THREAD = BM * BN / 256;
 };
@@ -383,14 +386,15 @@ __device__ __forceinline__ Acc mma_split(const u32x4& x, const u32x4& y, const A
 // Tile numbering of one launch.  Dense and table forms (pair_mode 0 / 1)
 // tile the stacked rows x stacked columns; the keyed form (pair_mode 2) tiles
 // each key's own 2^mb x 2^nb product (its operand variants from lidx / ridx,
-// swapped when A holds R), whose sides are multiples of the tile's.
+// swapped when A holds R); a key narrower than the tile leaves the tile's
+// other rows / columns unused.
 template <int BM, int BN>
 struct TileMap {
   int64_t tiles_m = 0, per_key = 0, tiles = 0;
   __device__ explicit TileMap(const ContractArgs& g) {
     if (g.pair_mode == 2) {
-      tiles_m = (int64_t(1) << g.mb) / BM;
-      per_key = tiles_m * ((int64_t(1) << g.nb) / BN);
+      tiles_m = ((int64_t(1) << g.mb) + BM - 1) / BM;
+      per_key = tiles_m * (((int64_t(1) << g.nb) + BN - 1) / BN);
       tiles = g.nvar * per_key;
     } else {
       const int64_t rowsA = g.nvarA << g.mb, rowsB = g.nvarB << g.nb;
@@ -398,9 +402,10 @@ struct TileMap {
       tiles = tiles_m * ((rowsB + BN - 1) / BN);
     }
   }
-  // First stacked row and column of `tile`, and its key (-1: not keyed).
+  // First stacked row and column of `tile`, its key (-1: not keyed), and the
+  // ends (exclusive) of the stacked rows and columns it may use.
   __device__ void origin(const ContractArgs& g, int64_t tile, int64_t& row0, int64_t& col0,
-                         int64_t& key) const {
+                         int64_t& key, int64_t& row_end, int64_t& col_end) const {
     if (g.pair_mode == 2) {
       key = tile / per_key;
       const int64_t t = tile - key * per_key;
@@ -409,10 +414,14 @@ struct TileMap {
       const uint32_t va = g.swapped ? vr : vl, vb = g.swapped ? vl : vr;
       row0 = (int64_t(va) << g.mb) + (t % tiles_m) * BM;
       col0 = (int64_t(vb) << g.nb) + (t / tiles_m) * BN;
+      row_end = int64_t(va + 1) << g.mb;
+      col_end = int64_t(vb + 1) << g.nb;
     } else {
       key = -1;
       row0 = (tile % tiles_m) * BM;
       col0 = (tile / tiles_m) * BN;
+      row_end = g.nvarA << g.mb;
+      col_end = g.nvarB << g.nb;
     }
   }
 };
@@ -448,12 +457,11 @@ __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* d
 template <int CFG>
 __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const float2* Ct,
                                                 int64_t row0, int64_t col0, int64_t key,
+                                                int64_t row_end, int64_t col_end,
                                                 const int64_t* dep_m_lo, const int64_t* dep_n_lo,
                                                 int r_tid, int c_tid) {
   using T = TileInfo<CFG, 0>;
   constexpr int BM = T::BM, BN = T::BN;
-  const int64_t rowsA = g.nvarA << g.mb;
-  const int64_t rowsB = g.nvarB << g.nb;
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t sizeC = M * N;
   const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.mapM) : 0;
@@ -473,7 +481,7 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
       }
     }
     const int64_t gr = row0 + r, gc = col0 + c;
-    if (gr >= rowsA || gc >= rowsB) continue;
+    if (gr >= row_end || gc >= col_end) continue;
     int64_t a = key;
     if (key < 0) {
       const int64_t rv = gr >> g.mb, cv = gc >> g.nb;
@@ -544,14 +552,14 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
   float4 ra[T::A_VEC], rb[T::B_VEC];
   // Loads the slab at k0 of a work item, zero beyond the item's K chunk end.
   auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    int64_t row0, col0, key;
-    tmap.origin(g, item % tiles, row0, col0, key);
+    int64_t row0, col0, key, row_end, col_end;
+    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
 #pragma unroll
     for (int t = 0; t < T::A_VEC; ++t) {
       const int e = tid + t * 256;
       const int r = e / (TK / 2), kp = e % (TK / 2);
       const int64_t gr = row0 + r, gk = k0 + 2 * kp;
-      ra[t] = (e < T::A_F4 && gr < rowsA && gk < klim)
+      ra[t] = (e < T::A_F4 && gr < row_end && gk < klim)
                   ? *reinterpret_cast<const float4*>(g.A + (gr << g.kb) + gk)
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -560,7 +568,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       const int e = tid + t * 256;
       const int r = e / (TK / 2), kp = e % (TK / 2);
       const int64_t gr = col0 + r, gk = k0 + 2 * kp;
-      rb[t] = (e < T::B_F4 && gr < rowsB && gk < klim)
+      rb[t] = (e < T::B_F4 && gr < col_end && gk < klim)
                   ? *reinterpret_cast<const float4*>(g.B + (gr << g.kb) + gk)
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -576,8 +584,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    int64_t row0, col0, key;
-    tmap.origin(g, item % tiles, row0, col0, key);
+    int64_t row0, col0, key, row_end, col_end;
+    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -733,7 +741,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
       });
     __syncthreads();
     if (grp == 0)
-      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, row_end, col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
   }
@@ -830,9 +838,9 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
     }
   };
   auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    int64_t row0, col0, key;
-    tmap.origin(g, item % tiles, row0, col0, key);
-    const int64_t la = rowsA - row0 - 1, lb = rowsB - col0 - 1;
+    int64_t row0, col0, key, row_end, col_end;
+    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
+    const int64_t la = row_end - row0 - 1, lb = col_end - col0 - 1;
     const bool full = k0 + TK <= klim;
     if (k0 >= klim) {
 #pragma unroll
@@ -861,8 +869,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    int64_t row0, col0, key;
-    tmap.origin(g, item % tiles, row0, col0, key);
+    int64_t row0, col0, key, row_end, col_end;
+    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -983,7 +991,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
       });
     __syncthreads();
     if (grp == 0)
-      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, row_end, col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
     p = pn;
   }
@@ -1031,9 +1039,9 @@ __global__ void __launch_bounds__(256) k_splitk_reduce(ContractArgs g) {
     for (int e = threadIdx.x; e < BM * BN; e += 256)
       Ct[(e / BN) * (BN + 1) + (e % BN)] = g.partial[tile * (BM * BN) + e];
     __syncthreads();
-    int64_t row0, col0, key;
-    tmap.origin(g, tile, row0, col0, key);
-    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, dep_m_lo, dep_n_lo, r_tid, c_tid));
+    int64_t row0, col0, key, row_end, col_end;
+    tmap.origin(g, tile, row0, col0, key, row_end, col_end);
+    amax = fmaxf(amax, epilogue_write<CFG>(g, Ct, row0, col0, key, row_end, col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
     __syncthreads();
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
@@ -1205,7 +1213,8 @@ unsigned persistent_grid(int64_t tiles) {
 
 // Tiles of a launch (see TileMap).
 int64_t launch_tiles(const ContractArgs& a, int bm, int bn) {
-  if (a.pair_mode == 2) return a.nvar * (((int64_t(1) << a.mb) / bm) * ((int64_t(1) << a.nb) / bn));
+  if (a.pair_mode == 2)
+    return a.nvar * ((((int64_t(1) << a.mb) + bm - 1) / bm) * (((int64_t(1) << a.nb) + bn - 1) / bn));
   const int64_t rowsA = a.nvarA << a.mb, rowsB = a.nvarB << a.nb;
   return ((rowsA + bm - 1) / bm) * ((rowsB + bn - 1) / bn);
 }
@@ -1256,7 +1265,10 @@ void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t ro
     }
     launch_cfg<1, PREC, lo>(a, s, rowsA, rowsB);
   } else {
-    launch_cfg<2, PREC, lo>(a, s, rowsA, rowsB);
+    if (a.tile == 3)
+      launch_cfg<3, PREC, lo>(a, s, rowsA, rowsB);
+    else
+      launch_cfg<2, PREC, lo>(a, s, rowsA, rowsB);
   }
 }
 
@@ -1272,8 +1284,8 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   if (a.pair_mode == 2) {
     int bm = 0, bn = 0;
     mfma_tile_shape(a.tile, &bm, &bn);
-    if (!a.lidx || !a.ridx || (int64_t(1) << a.mb) < bm || (int64_t(1) << a.nb) < bn || a.ksplit != 1)
-      throw std::invalid_argument("keyed MFMA form needs index arrays, keys of whole tiles, no split K");
+    if (!a.lidx || !a.ridx || (int64_t(2) << a.mb) < bm || (int64_t(2) << a.nb) < bn || a.ksplit != 1)
+      throw std::invalid_argument("keyed MFMA form needs index arrays, keys of at least half a tile side, no split K");
   }
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
@@ -1294,14 +1306,16 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
     launch_reduce_cfg<0>(a, s, rowsA, rowsB);
   else if (a.tile == 1)
     launch_reduce_cfg<1>(a, s, rowsA, rowsB);
-  else
+  else if (a.tile == 2)
     launch_reduce_cfg<2>(a, s, rowsA, rowsB);
+  else
+    launch_reduce_cfg<3>(a, s, rowsA, rowsB);
 }
 
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
   if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
-  if (tk == lo) return tile >= 0 && tile <= 2;
+  if (tk == lo) return tile >= 0 && tile <= 3;
   if (tk == 2 * lo) return tile == 0 || (prec == 0 && tile == 1);
   return false;
 }
@@ -1312,22 +1326,27 @@ void prepare_mfma_launch(int prec) {
   if (prec == 0) {
     (void)persistent_grid<0, 0, 16, 1>(1), (void)persistent_grid<1, 0, 16, 1>(1);
     (void)persistent_grid<2, 0, 16, 1>(1), (void)persistent_grid<0, 0, 32, 1>(1);
+    (void)persistent_grid<3, 0, 16, 1>(1);
     (void)persistent_grid<1, 0, 32, 1>(1), (void)persistent_grid<0, 0, 16, 2>(1);
     (void)persistent_grid<0, 0, 32, 2>(1);
   } else if (prec == 1) {
     (void)persistent_grid<0, 1, 32, 1>(1), (void)persistent_grid<1, 1, 32, 1>(1);
     (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
+    (void)persistent_grid<3, 1, 32, 1>(1);
     (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
     (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
     (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
+    (void)persistent_grid<3, 2, 32, 1>(1);
     (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  *bm = tile == 0 ? 64 : (tile == 1 ? 32 : 16);
-  *bn = tile == 0 ? 64 : (tile == 1 ? 128 : 256);
+  static const int kBM[4] = {64, 32, 16, 64}, kBN[4] = {64, 128, 256, 16};
+  const int t = tile >= 0 && tile < 4 ? tile : 0;
+  *bm = kBM[t];
+  *bn = kBN[t];
 }
 
 int64_t mfma_tiles(int tile, int64_t rowsA, int64_t rowsB) {

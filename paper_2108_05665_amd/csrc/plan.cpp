@@ -118,12 +118,12 @@ bool mfma_keyed_fits(const Node& nd, int tile, int swapped) {
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
   const int rb = swapped ? nd.nb : nd.mb, cb = swapped ? nd.mb : nd.nb;
-  return (int64_t(1) << rb) >= bm && (int64_t(1) << cb) >= bn;
+  return (int64_t(2) << rb) >= bm && (int64_t(2) << cb) >= bn;
 }
 
 bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb) {
   if (nd.kb < 1 || nd.kb > 21 || mfma_capable(nd, nvarL, nvarR, nb)) return false;
-  for (int tile = 0; tile < 3; ++tile)
+  for (int tile = 0; tile < kMfmaTiles; ++tile)
     for (int sw = 0; sw < 2; ++sw)
       if (mfma_keyed_fits(nd, tile, sw)) return true;
   return false;
@@ -208,12 +208,23 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
     const double keyed_work = useful / std::ldexp(1.0, nd.kb) *
                               std::max(std::ldexp(1.0, nd.kb), double(mfma_default_slab(prec)));
     if (useful < min_cmacs || 8 * useful < keyed_work) return;
-    for (int t = 0; t < 3; ++t)
-      for (int sw = 0; sw < 2; ++sw)
-        if (mfma_keyed_fits(nd, t, sw)) {
-          configure_mfma(nd, nvarL, nvarR, nb, t, sw, 1, mfma_default_slab(prec));
-          return;
+    // The fitting tile with the least padding (then the lower tile number).
+    int best_t = -1, best_sw = 0;
+    double best_pad = 0;
+    for (int t = 0; t < kMfmaTiles; ++t)
+      for (int sw = 0; sw < 2; ++sw) {
+        if (!mfma_keyed_fits(nd, t, sw)) continue;
+        int bm = 0, bn = 0;
+        mfma_tile_shape(t, &bm, &bn);
+        const double M = std::ldexp(1.0, sw ? nd.nb : nd.mb), N = std::ldexp(1.0, sw ? nd.mb : nd.nb);
+        const double pad = std::ceil(M / bm) * bm * std::ceil(N / bn) * bn / (M * N);
+        if (best_t < 0 || pad < best_pad) {
+          best_t = t;
+          best_sw = sw;
+          best_pad = pad;
         }
+      }
+    if (best_t >= 0) configure_mfma(nd, nvarL, nvarR, nb, best_t, best_sw, 1, mfma_default_slab(prec));
     return;
   }
   if (!mfma_capable(nd, nvarL, nvarR, nb) || rows < 8 || cols < 64 || useful < min_cmacs ||

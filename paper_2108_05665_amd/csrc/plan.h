@@ -132,8 +132,8 @@ struct DeviceGuard {
 // dense enough.
 bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
 // Keyed MFMA form (one GEMM per key): the stacked form does not apply and
-// each key's 2^mb x 2^nb product covers whole tiles of `tile` with the given
-// row operand.
+// each key's 2^mb x 2^nb product spans at least half of each side of `tile`
+// with the given row operand (at most 4x padding).
 bool mfma_keyed_fits(const Node& nd, int tile, int swapped);
 bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
 // Whether the MFMA kernel can run the node in this configuration.

@@ -445,9 +445,14 @@ def test_every_mfma_variant_vs_state_vector(precision):
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_fp16"])
-def test_keyed_form_vs_state_vector(precision):
+@pytest.mark.parametrize("shapes", [((0, 64, 64), (1, 32, 128), (2, 16, 256)), ((3, 64, 16),),
+                                    ((0, 32, 32), (3, 32, 8))],
+                         ids=["wide_tiles", "narrow_tile", "part_filled_tiles"])
+def test_keyed_form_vs_state_vector(precision, shapes):
     """The keyed MFMA form (one GEMM per key, operand variants from the key's
-    index pair) forced on every node whose keys fill a tile: amplitudes within
+    index pair) forced on every node whose keys span at least (rows, columns)
+    of `shapes` (the first that fits, either child as the row operand; the
+    last case leaves up to three quarters of a tile unused): amplitudes within
     the bound of the state vector, reruns bit-identical, and every forced node
     reports the keyed form."""
     tol = AMP_TOL if precision == "c64" else SPLIT_TOL
@@ -461,7 +466,7 @@ def test_keyed_form_vs_state_vector(precision):
     for ns in p.all_node_stats():
         if not 1 <= ns["k_bits"] <= 21:
             continue
-        for tile, bm, bn in ((0, 64, 64), (1, 32, 128), (2, 16, 256)):
+        for tile, bm, bn in shapes:
             for sw in (0, 1):
                 rows, cols = (ns["n_bits"], ns["m_bits"]) if sw else (ns["m_bits"], ns["n_bits"])
                 if (1 << rows) >= bm and (1 << cols) >= bn:
