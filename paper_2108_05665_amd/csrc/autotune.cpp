@@ -71,10 +71,11 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
       }
   }
   if (!stacked) return out;
+  // (The 64 x 16 tile serves narrow keyed products only.)
   for (int sw = 0; sw < 2; ++sw) {
     const double rows = double(sw ? nr : nl) * std::ldexp(1.0, sw ? nd.nb : nd.mb);
     const double cols = double(sw ? nl : nr) * std::ldexp(1.0, sw ? nd.mb : nd.nb);
-    for (int tile = 0; tile < kMfmaTiles; ++tile) {
+    for (int tile = 0; tile < 3; ++tile) {
       int bm = 0, bn = 0;
       mfma_tile_shape(tile, &bm, &bn);
       const double padded = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *

@@ -388,6 +388,12 @@ __device__ __forceinline__ Acc mma_split(const u32x4& x, const u32x4& y, const A
 // each key's own 2^mb x 2^nb product (its operand variants from lidx / ridx,
 // swapped when A holds R); a key narrower than the tile leaves the tile's
 // other rows / columns unused.
+struct TileOrigin {
+  int64_t row0, col0;        // first stacked row and column
+  int64_t key;               // the tile's key (keyed form), else -1
+  int64_t row_end, col_end;  // ends (exclusive) of the rows / columns it may use
+};
+
 template <int BM, int BN>
 struct TileMap {
   int64_t tiles_m = 0, per_key = 0, tiles = 0;
@@ -402,8 +408,11 @@ struct TileMap {
       tiles = tiles_m * ((rowsB + BN - 1) / BN);
     }
   }
-  // First stacked row and column of `tile`, its key (-1: not keyed), and the
-  // ends (exclusive) of the stacked rows and columns it may use.
+  __device__ TileOrigin at(const ContractArgs& g, int64_t tile) const {
+    TileOrigin o;
+    origin(g, tile, o.row0, o.col0, o.key, o.row_end, o.col_end);
+    return o;
+  }
   __device__ void origin(const ContractArgs& g, int64_t tile, int64_t& row0, int64_t& col0,
                          int64_t& key, int64_t& row_end, int64_t& col_end) const {
     if (g.pair_mode == 2) {
@@ -551,9 +560,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
 
   float4 ra[T::A_VEC], rb[T::B_VEC];
   // Loads the slab at k0 of a work item, zero beyond the item's K chunk end.
-  auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    int64_t row0, col0, key, row_end, col_end;
-    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
+  auto fetch = [&](const TileOrigin& o, int64_t k0, int64_t klim) {
+    const int64_t row0 = o.row0, col0 = o.col0, row_end = o.row_end, col_end = o.col_end;
 #pragma unroll
     for (int t = 0; t < T::A_VEC; ++t) {
       const int e = tid + t * 256;
@@ -580,12 +588,15 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
     if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
     return;
   }
-  fetch(item_of(p), k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
+  // Origin of the tile being multiplied (updated when the next tile's first
+  // slab is fetched).
+  TileOrigin cur = tmap.at(g, item_of(p) % tiles);
+  fetch(cur, k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    int64_t row0, col0, key, row_end, col_end;
-    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
+    const TileOrigin o = cur;
+    const int64_t row0 = o.row0, col0 = o.col0, key = o.key, row_end = o.row_end, col_end = o.col_end;
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -625,10 +636,12 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
         }
       }
       __syncthreads();
-      if (k0 + KG * TK < kend)
-        fetch(item, k0 + (KG + grp) * TK, kend);
-      else if (pn < walk)
-        fetch(item_of(pn), k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
+      if (k0 + KG * TK < kend) {
+        fetch(o, k0 + (KG + grp) * TK, kend);
+      } else if (pn < walk) {
+        cur = tmap.at(g, item_of(pn) % tiles);
+        fetch(cur, k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
+      }
 
       if constexpr (MF == 32) {
         const int i = lane & 31;
@@ -837,9 +850,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
       }
     }
   };
-  auto fetch = [&](int64_t item, int64_t k0, int64_t klim) {
-    int64_t row0, col0, key, row_end, col_end;
-    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
+  auto fetch = [&](const TileOrigin& o, int64_t k0, int64_t klim) {
+    const int64_t row0 = o.row0, col0 = o.col0, row_end = o.row_end, col_end = o.col_end;
     const int64_t la = row_end - row0 - 1, lb = col_end - col0 - 1;
     const bool full = k0 + TK <= klim;
     if (k0 >= klim) {
@@ -859,7 +871,10 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
     if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
     return;
   }
-  fetch(item_of(p), k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
+  // Origin of the tile being multiplied (updated when the next tile's first
+  // slab is fetched).
+  TileOrigin cur = tmap.at(g, item_of(p) % tiles);
+  fetch(cur, k_begin(item_of(p)) + grp * TK, k_begin(item_of(p)) + Kc);
 
   constexpr int GROUPS = MF == 32 ? 2 : 4;  // lane K groups of 8 halves per MFMA
   constexpr int KPM = 8 * GROUPS;           // K per MFMA
@@ -869,8 +884,8 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
 
   while (p < walk) {
     const int64_t item = item_of(p);
-    int64_t row0, col0, key, row_end, col_end;
-    tmap.origin(g, item % tiles, row0, col0, key, row_end, col_end);
+    const TileOrigin o = cur;
+    const int64_t row0 = o.row0, col0 = o.col0, key = o.key, row_end = o.row_end, col_end = o.col_end;
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
@@ -898,10 +913,12 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
         if (pi < NPB) split_store4<PREC>(rb[j][0], rb[j][1], sB, Bs + (pi / QR) * KP + 4 * (pi % QR), PL_B);
       }
       __syncthreads();
-      if (k0 + KG * TK < kend)
-        fetch(item, k0 + (KG + grp) * TK, kend);
-      else if (pn < walk)
-        fetch(item_of(pn), k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
+      if (k0 + KG * TK < kend) {
+        fetch(o, k0 + (KG + grp) * TK, kend);
+      } else if (pn < walk) {
+        cur = tmap.at(g, item_of(pn) % tiles);
+        fetch(cur, k_begin(item_of(pn)) + grp * TK, k_begin(item_of(pn)) + Kc);
+      }
 
 #pragma unroll
       for (int st = 0; st < STEPS; ++st) {
