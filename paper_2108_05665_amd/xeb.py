@@ -420,16 +420,7 @@ class BatchSet:
         self.amps = list(amps) if amps is not None else [p.new_amps() for p in self.plans]
         self.batches = []  # (Batch, indices into plans)
         self.eager = []    # indices run eagerly
-        est = [self._estimate(p) for p in self.plans]
-        groups, cur, tot = [], [], 0
-        for i, e in enumerate(est):
-            if cur and tot + e > 0.9 * max_nodes:
-                groups.append(cur)
-                cur, tot = [], 0
-            cur.append(i)
-            tot += e
-        if cur:
-            groups.append(cur)
+        groups = self.group([self._estimate(p) for p in self.plans], max_nodes)
         try:
             while groups:
                 g = groups.pop(0)
@@ -447,6 +438,22 @@ class BatchSet:
             self.close()
             raise
         self.eager.sort()
+
+    @staticmethod
+    def group(estimates, max_nodes: int = BATCH_MAX_NODES):
+        """Consecutive plan indices grouped greedily so that each group's
+        estimated launches stay within 90 % of max_nodes (a plan above that
+        alone forms a group of its own)."""
+        groups, cur, tot = [], [], 0
+        for i, e in enumerate(estimates):
+            if cur and tot + e > 0.9 * max_nodes:
+                groups.append(cur)
+                cur, tot = [], 0
+            cur.append(i)
+            tot += e
+        if cur:
+            groups.append(cur)
+        return groups
 
     @staticmethod
     def _estimate(p) -> int:

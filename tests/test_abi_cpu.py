@@ -279,3 +279,21 @@ def test_node_config_get_set_and_validation():
     leaf = 0
     with pytest.raises(xeb.XebError):
         p.node_config(leaf)
+
+
+def test_batch_grouping_under_the_graph_limit():
+    """BatchSet's grouping: consecutive plans, every plan in exactly one group,
+    no group of two or more above 90 % of the node limit, and the launch
+    estimate of a plan covers its node evaluations and slice sums."""
+    est = [10000, 20000, 30000, 90000, 5000, 5000, 40000, 1]
+    groups = xeb.BatchSet.group(est, 49152)
+    assert [i for g in groups for i in g] == list(range(len(est)))
+    for g in groups:
+        assert len(g) == 1 or sum(est[i] for i in g) <= 0.9 * 49152
+    assert [90000] in [[est[i] for i in g] for g in groups]
+    c = grid_circuit(3, 4, 6, 7)
+    s = uniform_bitstrings(12, 200, 8)
+    ch, sl, _ = planner.plan(c, s, n_sliced=2, trials=2)
+    p = xeb.Plan(c, s, ch, sl, bind=False)
+    st = p.stats()
+    assert xeb.BatchSet._estimate(p) >= st["evals_full"] + (1 << st["n_sliced"]) * st["n_blocks"]
