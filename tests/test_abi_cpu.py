@@ -297,3 +297,31 @@ def test_batch_grouping_under_the_graph_limit():
     p = xeb.Plan(c, s, ch, sl, bind=False)
     st = p.stats()
     assert xeb.BatchSet._estimate(p) >= st["evals_full"] + (1 << st["n_sliced"]) * st["n_blocks"]
+
+
+def test_share_53q_plan_compiles_at_full_size():
+    """Host side of the 53-qubit share at full size (6x9 minus one site, 14
+    cycles, 3*10^5 uniform strings, 22 sliced legs): the plan compiles within
+    a 250 GiB HBM budget by cutting the sorted strings into a power-of-two
+    number of blocks; the strings are all distinct (3*10^5 draws from 2^53),
+    and every node's key count obeys the per-block bound
+    |t_T| <= min(k_L k_R, 2^|slice bits| k) summed over the blocks (App. C)."""
+    from synth import config_circuit, config_bitstrings
+
+    c = config_circuit("share_53q_m14")
+    s = config_bitstrings("share_53q_m14", c.n_qubits)
+    assert c.n_qubits == 53 and len(s) == 300000
+    ch, sl, _ = planner.plan(c, s, n_sliced=22, trials=2, seed=0, anneal_steps=20000,
+                             anneal_restarts=1, workers=1, table_bytes_max=200 << 30)
+    budget = 250 << 30
+    p = xeb.Plan(c, s, ch, sl, bind=False, memory_budget=budget)
+    st = p.stats()
+    assert st["k"] == 300000 and st["k_distinct"] == 300000
+    assert st["n_sliced"] == 22
+    assert st["workspace_bytes"] <= budget
+    nb = st["n_blocks"]
+    assert nb >= 1 and nb & (nb - 1) == 0
+    for ns in p.all_node_stats():
+        slice_keys = 1 << bin(ns["slice_mask"]).count("1")
+        assert 1 <= ns["variants"] <= ns["left_variants"] * ns["right_variants"]
+        assert ns["variants"] <= nb * slice_keys * 300000
