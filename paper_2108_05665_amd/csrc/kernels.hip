@@ -2,14 +2,13 @@
 //
 // * contract_generic: one thread per output element of every variant; the
 //   path for small or sparse nodes (latency-bound).
-// * contract_mfma: the variants of L stacked as rows (nvarA * 2^mb rows of
-//   2^kb complex) times the variants of R stacked as rows, on FP32 MFMA
-//   (v_mfma_f32_32x32x2_f32).  A complex product takes two MFMAs per complex
-//   k: the instruction's K = 2 runs over (re, im) of the row operand, and the
-//   column operand supplies (re, -im) for the real part and (im, re) for the
-//   imaginary part, so every complex MAC costs exactly 4 real MACs.
-//   The epilogue scatters each output element straight into the layout the
+// * contract_mfma (complex64 on FP32 MFMA) and contract_split (hi/lo
+//   FP16 / BF16 on 16-bit MFMA): the variants of L stacked as rows
+//   (nvarA * 2^mb rows of 2^kb complex) times the variants of R stacked as
+//   rows, or, for key sets too sparse to stack, one product per key.  The
+//   epilogue scatters each output element straight into the layout the
 //   parent node reads (bit deposit), so no separate transpose pass exists.
+// * splitk_sum / splitk_reduce: the chunk sum of split-K nodes.
 // * accumulate / fold_compensation: FP64 Neumaier sum over slices.
 // * xeb: compensated FP64 reduction of sum |amp|^2 in a fixed order.
 
@@ -239,8 +238,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// MFMA contraction (stacked-key complex GEMM  C = A . B^T, both operands with
-// their K legs contiguous).
+// MFMA contraction (complex GEMM  C = A . B^T over stacked keys, or one per
+// key in the keyed form; both operands with their K legs contiguous).
 //
 // Tile shapes (workgroup of four waves):
 //   0: 64 x 64,  waves 2 x 2, one 32 x 32 block each
@@ -257,9 +256,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //     in [2^14, 2^15)), becomes hi = round(x 2^e), lo = round(x 2^e - hi); the
 //     products hi.hi + hi.lo + lo.hi accumulate in FP32 on
 //     v_mfma_f32_32x32x16 / 16x16x32 (lo.lo is dropped) and the result is
-//     scaled back by 2^-(eA + eB).  LDS holds hi / lo planes [row][realified k]
-//     with (re, im) interleaved; the column operand's (re, -im) and (im, re)
-//     forms are a sign flip and a 16-bit rotation of each packed pair.
+//     scaled back by 2^-(eA + eB).  LDS holds four planes per operand (hi re,
+//     hi im, lo re, lo im), rows of TK + 8 halves (see k_contract_split).
 // K is staged TK complex at a time (a template parameter: 16 or 32 for
 // complex64, 32 or 64 for the split forms; larger slabs keep more bytes in
 // flight per barrier, smaller ones need fewer registers).
