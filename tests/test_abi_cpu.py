@@ -325,3 +325,45 @@ def test_share_53q_plan_compiles_at_full_size():
         slice_keys = 1 << bin(ns["slice_mask"]).count("1")
         assert 1 <= ns["variants"] <= ns["left_variants"] * ns["right_variants"]
         assert ns["variants"] <= nb * slice_keys * 300000
+
+
+def test_sparse_batch_nodes_default_to_the_keyed_form():
+    """In the stored batch plans, the MFMA nodes whose key sets are too sparse
+    for the stacked product (more than 8 child key pairs per key) run keyed by
+    default: no split K, each key's block spans at least half of each side of
+    the tile, and the tile and orientation are the ones with the least
+    padding."""
+    from synth import batch_spec, batch_circuit
+
+    path = os.path.join(os.path.dirname(__file__), "data", "batch32_plans.json")
+    with open(path) as f:
+        saved = json.load(f)
+    shapes = {0: (64, 64), 1: (32, 128), 2: (16, 256), 3: (64, 16)}
+    seen = 0
+    for i in (0, 5, 6, 9):
+        rec = [r for r in saved["plans"] if r["i"] == i][0]
+        sp, circ = batch_spec(i), batch_circuit(i)
+        strings = uniform_bitstrings(circ.n_qubits, sp["k"], sp["string_seed"])
+        p = xeb.Plan(circ, strings, rec["children"], rec["sliced"], memory_budget=saved["budget"],
+                     bind=False)
+        assert p.stats()["n_blocks"] >= 1
+        for ns in p.all_node_stats():
+            if ns["kernel"] != "mfma" or ns["pair_mode"] != 2:
+                continue
+            seen += 1
+            assert ns["left_variants"] * ns["right_variants"] > 8 * ns["variants"]
+            assert ns["ksplit"] == 1 and 1 <= ns["k_bits"] <= 21
+
+            def pad(tile, sw):
+                bm, bn = shapes[tile]
+                M = 1 << (ns["n_bits"] if sw else ns["m_bits"])
+                N = 1 << (ns["m_bits"] if sw else ns["n_bits"])
+                if 2 * M < bm or 2 * N < bn:
+                    return None
+                return (-(-M // bm) * bm) * (-(-N // bn) * bn) / (M * N)
+
+            got = pad(ns["tile"], ns["swapped"])
+            assert got is not None
+            best = min(x for x in (pad(t, w) for t in shapes for w in (0, 1)) if x is not None)
+            assert got == best
+    assert seen >= 4
