@@ -319,10 +319,16 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Scale exponent e with amax 2^e in [2^14, 2^15) (0 for an all-zero tensor),
 // from a table's n amax slots.
+// The n <= 64 slots are read by one vector load across the wave (lane i
+// reads slot i) and reduced with shuffles: one memory round trip instead of n
+// dependent scalar loads at every workgroup's start.
 __device__ __forceinline__ int fp16_scale_exp(const unsigned long long* slots, int n) {
-  unsigned long long w = 0;
-  for (int i = 0; i < n; ++i) {
-    const unsigned long long v = slots[i * kAmaxStride];
+  const int lane = threadIdx.x & 63;
+  unsigned long long w = lane < n ? slots[lane * kAmaxStride] : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t hi = __shfl_xor(uint32_t(w >> 32), o), lo = __shfl_xor(uint32_t(w), o);
+    const unsigned long long v = (static_cast<unsigned long long>(hi) << 32) | lo;
     w = v > w ? v : w;
   }
   const float m = __uint_as_float(uint32_t(w));
