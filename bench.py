@@ -10,10 +10,10 @@ contraction with the memo tables (all 2^10 slices), the FP64 cross-slice sum
 and the XEB reduction.  Planning (tree, slicing, plan compilation) happens
 once before the timed region and is reported separately.
 
-Both precisions run: split-FP16 MFMA products (the headline `value`) and
-plain complex64 on FP32 MFMA, with the speedup and the split-vs-c64 amplitude
-and XEB differences over all strings, and sampled per-slice partials checked
-against the FP64 oracle for each.  Each precision is timed in two launch
+Three precisions run: split-FP16 MFMA products (the headline `value`),
+split-BF16 products, and plain complex64 on FP32 MFMA, with the speedups and
+the split-vs-c64 amplitude and XEB differences over all strings, and sampled
+per-slice partials checked against the FP64 oracle for each.  Each precision is timed in two launch
 forms: eager (one host launch per node evaluation) and the hipGraph batch
 form (the same launches captured once, one graph launch per step; `value`).
 The timed steps carry no profiling events; a separate eager pass with HIP
@@ -144,8 +144,9 @@ def main() -> int:
     ap.add_argument("--trials", type=int, default=16, help="planner greedy trials")
     ap.add_argument("--anneal-steps", type=int, default=500000, help="tree optimizer steps")
     ap.add_argument("--anneal-restarts", type=int, default=6)
-    ap.add_argument("--precisions", default="split_fp16,c64",
-                    help="comma list; the first one gives `value`")
+    ap.add_argument("--precisions", default=None,
+                    help="comma list; the first one gives `value` (default: split_fp16, "
+                         "split_bf16, c64; batch32: split_fp16, c64)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
@@ -176,6 +177,8 @@ def main() -> int:
                     help="first run a plain scale kernel (read + write of this many MiB) "
                          "whose HBM counters calibrate the contraction's")
     args = ap.parse_args()
+    if args.precisions is None:
+        args.precisions = "split_fp16,c64" if args.workload == "batch32" else "split_fp16,split_bf16,c64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(slices would shard across GPUs with one all-reduce of the amplitudes)",
