@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxeb.so")
 
-SOURCES = ["network.cpp", "plan.cpp", "autotune.cpp", "batch.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["network.cpp", "plan.cpp", "autotune.cpp", "batch.cpp", "api.cpp", "kernels.hip",
+           "fidelity.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -106,7 +106,12 @@ void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t*
                        double2* amps, double2* comp, int64_t n, hipStream_t s);
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s);
 
-// Linear XEB (Eq. 1): out[0] = 2^n / k * sum |amps|^2 - 1.
-void launch_xeb(const double2* amps, int64_t k, int n_qubits, double* out, hipStream_t s);
+// Linear XEB (Eq. 1): F = 2^n / k * sum |amps|^2 - 1, a compensated FP64
+// reduction in a fixed order over chunks of kXebChunk strings (two kernels).
+// `scratch` (device, 16-byte aligned, xeb_scratch_bytes(k) bytes) receives F
+// in its first double; the rest holds the chunks' partial sums.
+constexpr int64_t kXebChunk = 4096;
+uint64_t xeb_scratch_bytes(int64_t k);
+void launch_xeb(const double2* amps, int64_t k, int n_qubits, void* scratch, hipStream_t s);
 
 }  // namespace xeb

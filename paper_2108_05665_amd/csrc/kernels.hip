@@ -10,13 +10,14 @@
 //   parent node reads (bit deposit), so no separate transpose pass exists.
 // * splitk_sum / splitk_reduce: the chunk sum of split-K nodes.
 // * accumulate / fold_compensation: FP64 Neumaier sum over slices.
-// * xeb: compensated FP64 reduction of sum |amp|^2 in a fixed order.
+// (The XEB reduction lives in fidelity.hip.)
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
 
+#include "compensated.h"
 #include "kernels.h"
 
 namespace xeb {
@@ -1075,15 +1076,6 @@ __global__ void k_zero(uint32_t* p, uint64_t words) {
     p[i] = 0u;
 }
 
-__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
-  const double t = s + x;
-  if (fabs(s) >= fabs(x))
-    c += (s - t) + x;
-  else
-    c += (x - t) + s;
-  s = t;
-}
-
 __global__ void k_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
                              double2* amps, double2* comp, int64_t n) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1105,44 +1097,6 @@ __global__ void k_fold(double2* amps, const double2* comp, int64_t k) {
   s.x += c.x;
   s.y += c.y;
   amps[i] = s;
-}
-
-// Error-free sum of two doubles (Knuth's TwoSum).
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-  s = a + b;
-  const double bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-constexpr int XEB_THREADS = 1024;
-
-__global__ void __launch_bounds__(XEB_THREADS) k_xeb(const double2* amps, int64_t k, int n,
-                                                     double* out) {
-  __shared__ double ss[XEB_THREADS];
-  __shared__ double cc[XEB_THREADS];
-  const int t = threadIdx.x;
-  double s = 0.0, c = 0.0;
-  for (int64_t i = t; i < k; i += XEB_THREADS) {
-    const double2 a = amps[i];
-    const double p = a.x * a.x + a.y * a.y;
-    neumaier(s, c, p);
-  }
-  ss[t] = s;
-  cc[t] = c;
-  __syncthreads();
-  for (int w = XEB_THREADS / 2; w > 0; w >>= 1) {
-    if (t < w) {
-      double sum, err;
-      two_sum(ss[t], ss[t + w], sum, err);
-      ss[t] = sum;
-      cc[t] = cc[t] + cc[t + w] + err;
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    const double total = ss[0] + cc[0];
-    out[0] = ldexp(total, n) / double(k) - 1.0;
-  }
 }
 
 struct LaunchEvents {
@@ -1392,10 +1346,6 @@ void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t*
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s) {
   if (k <= 0) return;
   k_fold<<<grid_for(k, 256), 256, 0, s>>>(amps, comp, k);
-}
-
-void launch_xeb(const double2* amps, int64_t k, int n_qubits, double* out, hipStream_t s) {
-  k_xeb<<<1, XEB_THREADS, 0, s>>>(amps, k, n_qubits, out);
 }
 
 }  // namespace xeb

@@ -600,7 +600,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     p.off_comp = off;
     off += align_up(uint64_t(k) * 16);
     p.off_scratch = off;
-    off += kAlign;
+    off += align_up(xeb_scratch_bytes(k));
     p.ws_bytes = off;
     if (o.trace > 1)
       std::fprintf(stderr,

@@ -266,3 +266,57 @@ def test_memo_with_slices():
     amps, runs = memo.memo_amplitudes(net, tree, strings, sliced)
     assert np.max(np.abs(amps - psi[np.array(strings)])) < 1e-12
     assert runs == memo.distinct_key_counts(net, tree, strings, sliced, range(8))
+
+
+def test_search_order_reproduces_state_vector():
+    """tn.search_order (the plain greedy and its perturbed variants, best under
+    a size cap) returns a valid order whose contraction equals the state
+    vector on a 20-qubit network, unsliced and summed over slices; the
+    perturbed branch alone (greedy_order with noise) is checked the same way."""
+    import random
+
+    c = grid_circuit(4, 5, 6, 51)
+    net = build_network(c)
+    psi = statevec.state_vector(c)
+    internal = [l for l in range(net.n_legs) if net.leg_qubit[l] < 0]
+    rng = np.random.Generator(np.random.PCG64(52))
+    sliced = [int(x) for x in rng.choice(internal, size=3, replace=False)]
+    strings = [int(x) for x in uniform_bitstrings(20, 3, 53)]
+    for sl in ((), sliced):
+        sets = tn.closed_leg_sets(net, sl)
+        for pairs, big, madds in (tn.search_order(sets, trials=16, cap_log2=12),
+                                  tn.greedy_order(sets, random.Random(7), noise=0.5)):
+            # an SSA order: every tensor consumed exactly once, one result left
+            used = [x for p in pairs for x in p]
+            assert len(used) == len(set(used)) == 2 * (len(sets) - 1)
+            assert set(used) == set(range(2 * len(sets) - 2))
+            for s in strings:
+                a = tn.amplitude(net, s, sl, pairs=pairs)
+                assert abs(a - psi[s]) < 1e-12
+
+
+def test_medium_golden_amplitudes_cross_check():
+    """The stored 36-qubit oracle amplitudes (tests/golden/medium_6x6_m12_amps64.json,
+    written by tests/golden/make_medium_amps.py): one of its O2 cross-check
+    partials recomputed here in the oracle's own greedy order, independent of
+    the plan's tree, equals both stored values; every stored amplitude is
+    finite and nonzero, and the strings are the workload's first 64."""
+    import json
+    import os
+
+    from synth import config_circuit, config_bitstrings
+
+    with open(os.path.join(GOLDEN, "medium_6x6_m12_amps64.json")) as f:
+        gold = json.load(f)
+    circ = config_circuit("medium_6x6_m12")
+    strings = config_bitstrings("medium_6x6_m12", circ.n_qubits)
+    assert gold["strings"] == [str(int(s)) for s in strings[:64]]
+    amps = np.array([complex(re, im) for re, im in gold["amps"]])
+    assert np.all(np.isfinite(amps)) and np.all(np.abs(amps) > 0)
+    net = build_network(circ)
+    sl = gold["sliced_legs"]
+    chk = gold["o2_cross_checks"][0]
+    pairs = tn.search_order(tn.closed_leg_sets(net, sl), trials=8)[0]
+    o2 = tn.partial_amplitude(net, int(strings[chk["string_index"]]), sl, chk["sigma"], pairs=pairs)
+    for stored in (chk["o2"], chk["memo"]):
+        assert abs(o2 - complex(*stored)) <= 1e-12 * abs(o2)
