@@ -6,8 +6,9 @@ closing layer, 10^4 seeded bitstrings whose qubits 0..19 share one fixed
 value (the rest uniform), sliced over 10 legs (2^10 slices).
 
 A step is one pass of the whole hot path over the batch: every slice's
-contraction with the memo tables (all 2^10 slices), the FP64 cross-slice sum
-and the XEB reduction.  Planning (tree, slicing, plan compilation) happens
+contraction with the memo tables (all 2^10 slices, 2^6 consecutive slices per
+contraction step by default: the low slice bits are stacked into the table
+keys), the FP64 cross-slice sum and the XEB reduction.  Planning (tree, slicing, plan compilation) happens
 once before the timed region and is reported separately.
 
 Three precisions run: split-FP16 MFMA products (the headline `value`),
@@ -203,6 +204,9 @@ def main() -> int:
     ap.add_argument("--configs", metavar="PATH",
                     help="apply node configurations from a --save-configs file instead of "
                          "autotuning (the same kernels in every run, e.g. for counters)")
+    ap.add_argument("--stack-slices", type=int, default=6,
+                    help="evaluate 2^J consecutive slices per contraction step "
+                         "(xeb_options_t.stack_slices; 0 = one slice at a time)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager form only (value then comes from it)")
     ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch32"],
@@ -283,7 +287,8 @@ def main() -> int:
     saved_configs = {}
     for prec in precs:
         t0 = time.perf_counter()
-        plan = xeb.Plan(circ, strings, children, sliced, device=0, precision=prec)
+        plan = xeb.Plan(circ, strings, children, sliced, device=0, precision=prec,
+                        stack_slices=args.stack_slices)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
         tune = None
@@ -425,6 +430,7 @@ def main() -> int:
             "strings": int(len(strings)),
             "distinct_strings": int(st["k_distinct"]),
             "slices": n_slices,
+            "slices_per_step": 1 << args.stack_slices,
             "precision": head,
             "launch_form": "eager" if r["t_capture"] is None else "hipgraph",
         },

@@ -112,6 +112,17 @@ typedef struct {
                              1 = never split, else a power of two bounding the split */
   double mfma_min_cmacs;  /* a node evaluation with fewer complex MACs than this (or
                              fewer than 8 rows) uses the generic kernel; 0 = default 2^23 */
+  int32_t stack_slices;   /* J, 0 <= J <= s and n_qubits + J <= 64 (default 0): the J
+                             lowest slice-id bits are evaluated together.  Their sliced
+                             legs become variables exactly like output legs (Appendix A,
+                             "Slicing": a sliced leg is summed over its values; section
+                             "Multi-batch simulator": fixed legs make leaves variables),
+                             so every node keeps one table entry per distinct (string
+                             key, low slice key) and one xeb_contract step covers 2^J
+                             consecutive slices.  Tables of nodes that depend on those
+                             bits grow by 2^(their count); launches fall by up to 2^J,
+                             and a node whose low slice bits are sparse is no longer
+                             recomputed for slices that do not change its key. */
 } xeb_options_t;
 
 typedef struct {
@@ -121,7 +132,8 @@ typedef struct {
   int64_t k_distinct;        /* distinct strings */
   int32_t n_qubits;
   int32_t n_sliced;          /* s; the plan has 2^s slices */
-  int64_t sum_variants;      /* sum over internal nodes of |t_T| (string variants) */
+  int64_t sum_variants;      /* sum over internal nodes of |t_T| (distinct keys: string key
+                                and, with stacked slices, low slice key) */
   int64_t max_tensor_elems;  /* largest tensor per variant (after slicing), elements */
   double cmacs_per_slice;    /* sum_T |t_T| 2^(q_T+r_T): one evaluation of every node */
   double cmacs_full;         /* complex MACs for all 2^s slices under the plan's schedule */
@@ -129,6 +141,7 @@ typedef struct {
   double evals_full;         /* node evaluations (kernel launches) for all slices */
   uint64_t workspace_bytes;
   int64_t n_blocks;          /* string blocks chosen by the dry run (1 = all strings at once) */
+  int32_t n_stacked;         /* J of xeb_options_t.stack_slices */
 } xeb_stats_t;
 
 #define XEB_KERNEL_GENERIC 0  /* per-element kernel (small or sparse nodes) */

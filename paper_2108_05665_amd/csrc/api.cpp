@@ -194,7 +194,10 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->m_bits = nd.mb;
     st->n_bits = nd.nb;
     st->k_bits = nd.kb;
-    st->slice_mask = nd.smask;
+    // Slice-id numbering: looped bits above the stacked ones, stacked bits
+    // from the key bits n .. n + sj - 1.
+    const uint64_t stacked = p.sj > 0 ? (nd.outmask >> p.n_qubits) & ((uint64_t(1) << p.sj) - 1) : 0;
+    st->slice_mask = (nd.smask << p.sj) | stacked;
     const xeb::NodeBlock& nb = p.blocks.front().nodes[node - p.n_leaves];
     st->kernel = nb.kernel;
     st->swapped = nb.kernel == XEB_KERNEL_MFMA ? nb.swapped : 0;

@@ -1076,15 +1076,20 @@ __global__ void k_zero(uint32_t* p, uint64_t words) {
     p[i] = 0u;
 }
 
-__global__ void k_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
-                             double2* amps, double2* comp, int64_t n) {
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int64_t i = idx[j];
-  const float2 p = partial[rho[j]];
+__global__ void k_accumulate(const float2* partial, const int32_t* idx, const int32_t* eoff,
+                             const int32_t* rho, const int32_t* slo, int64_t base, int64_t lo,
+                             int64_t hi, double2* amps, double2* comp, int64_t n) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int64_t i = idx[g];
   double2 s = amps[i], c = comp[i];
-  neumaier(s.x, c.x, double(p.x));
-  neumaier(s.y, c.y, double(p.y));
+  for (int32_t j = eoff[g], end = eoff[g + 1]; j < end; ++j) {
+    const int64_t sigma = base + slo[j];
+    if (sigma < lo || sigma >= hi) continue;
+    const float2 p = partial[rho[j]];
+    neumaier(s.x, c.x, double(p.x));
+    neumaier(s.y, c.y, double(p.y));
+  }
   amps[i] = s;
   comp[i] = c;
 }
@@ -1336,11 +1341,12 @@ void launch_zero(void* p, uint64_t bytes, hipStream_t s) {
   k_zero<<<grid_for(int64_t(words), 256), 256, 0, s>>>(static_cast<uint32_t*>(p), words);
 }
 
-void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* rho,
-                       double2* amps, double2* comp, int64_t n, hipStream_t s) {
+void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* eoff,
+                       const int32_t* rho, const int32_t* slo, int64_t base, int64_t lo,
+                       int64_t hi, double2* amps, double2* comp, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  launch(k_accumulate, dim3(grid_for(n, 256)), dim3(256), s, true, true, partial, idx, rho, amps,
-         comp, n);
+  launch(k_accumulate, dim3(grid_for(n, 256)), dim3(256), s, true, true, partial, idx, eoff, rho,
+         slo, base, lo, hi, amps, comp, n);
 }
 
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s) {

@@ -296,7 +296,11 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   // ---- sliced legs --------------------------------------------------------
   if (s < 0 || s > 40) fail(XEB_EINVAL, "number of sliced legs must be in [0, 40]");
   if (s > 0 && !sliced) fail(XEB_EINVAL, "sliced legs is NULL");
+  const int J = o.stack_slices;
+  if (J < 0 || J > s) fail(XEB_EINVAL, "stack_slices must be in [0, s]");
+  if (n + J > 64) fail(XEB_EINVAL, "n_qubits + stack_slices exceeds 64 key bits");
   p.s = s;
+  p.sj = J;
   p.sliced.assign(sliced, sliced + s);
   std::vector<int> slot(net.n_legs, -1);
   for (int j = 0; j < s; ++j) {
@@ -314,8 +318,10 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       const int q = net.leg_qubit[leg];
       if (q >= 0)
         nd.outmask |= uint64_t(1) << q;
+      else if (slot[leg] >= 0 && slot[leg] < J)
+        nd.outmask |= uint64_t(1) << (n + slot[leg]);  // stacked: a key bit
       else if (slot[leg] >= 0)
-        nd.smask |= uint64_t(1) << slot[leg];
+        nd.smask |= uint64_t(1) << (slot[leg] - J);
       else
         nd.legs.push_back(leg);
     }
@@ -375,22 +381,36 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   }
 
   // ---- strings in lexicographic tuple order (Appendix C) --------------------
-  // A string's tuple lists its leaf keys in depth-first leaf order; with every
-  // output qubit on exactly one leaf the concatenated keys fit in 64 bits.
-  std::vector<uint64_t> ds(bits, bits + k);
-  std::sort(ds.begin(), ds.end());
-  ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
-  const int64_t kd = int64_t(ds.size());
+  // Keyed strings: every distinct string with every low slice key, the slice
+  // key in bits n .. n + J - 1.  A keyed string's tuple lists its leaf keys
+  // in depth-first leaf order; a stacked slice bit sits on the two leaves its
+  // leg joins, and only its first occurrence enters the sort key, so the
+  // concatenated key has n + J <= 64 bits.
+  std::vector<uint64_t> dr(bits, bits + k);
+  std::sort(dr.begin(), dr.end());
+  dr.erase(std::unique(dr.begin(), dr.end()), dr.end());
+  const int64_t kdr = int64_t(dr.size());
+  const int64_t kd = kdr << J;
+  if (kd > (int64_t(1) << 31) - 1) fail(XEB_EINVAL, "distinct strings times 2^stack_slices exceed 2^31 - 1");
+  std::vector<uint64_t> ds(kd);
+  for (int64_t i = 0; i < kdr; ++i)
+    for (int64_t sl = 0; sl < (int64_t(1) << J); ++sl)
+      ds[(i << J) | sl] = dr[i] | (J > 0 ? uint64_t(sl) << n : 0);
   p.k = k;
   p.kd = kd;
   std::vector<int> dfs;
   leaves_dfs(p.nodes, p.root, dfs);
   {
+    std::vector<uint64_t> first_bits;  // per DFS leaf: its key bits not seen before
+    uint64_t seen = 0;
+    for (int j : dfs) {
+      first_bits.push_back(p.nodes[j].outmask & ~seen);
+      seen |= p.nodes[j].outmask;
+    }
     std::vector<std::pair<uint64_t, uint64_t>> keyed(kd);
     for (int64_t i = 0; i < kd; ++i) {
       uint64_t key = 0;
-      for (int j : dfs) {
-        const uint64_t om = p.nodes[j].outmask;
+      for (uint64_t om : first_bits) {
         if (!om) continue;
         const int w = popcount64(om);
         key = (w == 64 ? 0 : (key << w)) | pext64(ds[i], om);
@@ -417,18 +437,21 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     for (int64_t i = 0; i < kd; ++i)
       leaf_var[j][i] = int32_t(std::lower_bound(uk.begin(), uk.end(), keys[i]) - uk.begin());
   }
-  // Position of every input string among the sorted distinct strings.
-  std::vector<int64_t> where(k);
+  // Position among the sorted keyed strings of (distinct string r, low slice
+  // key sl): pos_of[(r << J) | sl], r indexing the ascending distinct strings.
+  std::vector<int64_t> pos_of(kd);
   {
-    std::vector<std::pair<uint64_t, int64_t>> sorted_pos(kd);
-    for (int64_t i = 0; i < kd; ++i) sorted_pos[i] = {ds[i], i};
-    std::sort(sorted_pos.begin(), sorted_pos.end());
-    for (int64_t i = 0; i < k; ++i) {
-      auto it = std::lower_bound(sorted_pos.begin(), sorted_pos.end(),
-                                 std::make_pair(bits[i], int64_t(-1)));
-      where[i] = it->second;
+    const uint64_t real = n < 64 ? (uint64_t(1) << n) - 1 : ~uint64_t(0);
+    for (int64_t j = 0; j < kd; ++j) {
+      const uint64_t x = ds[j];
+      const int64_t r = std::lower_bound(dr.begin(), dr.end(), x & real) - dr.begin();
+      const int64_t sl = J > 0 ? int64_t(x >> n) : 0;
+      pos_of[(r << J) | sl] = j;
     }
   }
+  // Distinct string of every input string.
+  std::vector<int64_t> where(k);
+  for (int64_t i = 0; i < k; ++i) where[i] = std::lower_bound(dr.begin(), dr.end(), bits[i]) - dr.begin();
 
   // Keys of every internal node among the strings [first, first + count).
   auto build_block = [&](int64_t first, int64_t count) {
@@ -450,9 +473,29 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       std::vector<int64_t> codes(count);
       for (int64_t i = 0; i < count; ++i)
         codes[i] = int64_t(var_of(nd.left, i)) * nr + var_of(nd.right, i);
-      std::vector<int64_t> uc(codes);
-      std::sort(uc.begin(), uc.end());
-      uc.erase(std::unique(uc.begin(), uc.end()), uc.end());
+      // Distinct codes in increasing order and each string's rank among them:
+      // a mark table over all (left, right) pairs when it is not much larger
+      // than the strings, else a sort.
+      const int64_t npairs = nvar_of(nd.left) * nr;
+      std::vector<int64_t> uc;
+      var[T].resize(count);
+      if (npairs <= std::max<int64_t>(4 * count, int64_t(1) << 22)) {
+        std::vector<int32_t> rank(size_t(npairs), 0);
+        for (int64_t i = 0; i < count; ++i) rank[size_t(codes[i])] = 1;
+        int32_t next = 0;
+        for (int64_t c2 = 0; c2 < npairs; ++c2)
+          if (rank[size_t(c2)]) {
+            rank[size_t(c2)] = next++;
+            uc.push_back(c2);
+          }
+        for (int64_t i = 0; i < count; ++i) var[T][i] = rank[size_t(codes[i])];
+      } else {
+        uc = codes;
+        std::sort(uc.begin(), uc.end());
+        uc.erase(std::unique(uc.begin(), uc.end()), uc.end());
+        for (int64_t i = 0; i < count; ++i)
+          var[T][i] = int32_t(std::lower_bound(uc.begin(), uc.end(), codes[i]) - uc.begin());
+      }
       if (uc.empty()) uc.push_back(0);
       nb.nvar = int64_t(uc.size());
       nb.lidx.resize(nb.nvar);
@@ -461,20 +504,26 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
         nb.lidx[v] = int32_t(uc[v] / nr);
         nb.ridx[v] = int32_t(uc[v] % nr);
       }
-      var[T].resize(count);
-      for (int64_t i = 0; i < count; ++i)
-        var[T][i] = int32_t(std::lower_bound(uc.begin(), uc.end(), codes[i]) - uc.begin());
       if (!p.nodes[nd.left].leaf) std::vector<int32_t>().swap(var[nd.left]);
       if (!p.nodes[nd.right].leaf) std::vector<int32_t>().swap(var[nd.right]);
       choose_kernel(nd, nvar_of(nd.left), nr, nb, o.force_generic != 0, o.max_ksplit,
                     o.mfma_min_cmacs > 0 ? o.mfma_min_cmacs : kMfmaMinCmacs, o.precision);
     }
     for (int64_t i = 0; i < k; ++i) {
-      const int64_t d = where[i];
-      if (d < first || d >= first + count) continue;
-      blk.idx.push_back(int32_t(i));
-      blk.rho.push_back(L == 1 ? leaf_var[0][d] : var[p.root][d - first]);
+      bool any = false;
+      for (int64_t sl = 0; sl < (int64_t(1) << J); ++sl) {
+        const int64_t d = pos_of[(where[i] << J) | sl];
+        if (d < first || d >= first + count) continue;
+        if (!any) {
+          blk.idx.push_back(int32_t(i));
+          blk.eoff.push_back(int32_t(blk.rho.size()));
+          any = true;
+        }
+        blk.rho.push_back(L == 1 ? leaf_var[0][d] : var[p.root][d - first]);
+        blk.slo.push_back(int32_t(sl));
+      }
     }
+    blk.eoff.push_back(int32_t(blk.rho.size()));
     return blk;
   };
 
@@ -502,8 +551,12 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       }
       blk.off_idx = off;
       off += align16(blk.idx.size() * 4);
+      blk.off_eoff = off;
+      off += align16(blk.eoff.size() * 4);
       blk.off_rho = off;
       off += align16(blk.rho.size() * 4);
+      blk.off_slo = off;
+      off += align16(blk.slo.size() * 4);
     }
     p.off_leaf_amax = off;
     off += align_up(uint64_t(nn) * 8);
@@ -662,8 +715,10 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
               bit = int((e >> axis_pos[a]) & 1);
             else if (net.leg_qubit[leg] >= 0)
               bit = int((nd.leaf_keys[v] >> rank_in_mask(nd.outmask, net.leg_qubit[leg])) & 1);
+            else if (slot[leg] < J)
+              bit = int((nd.leaf_keys[v] >> rank_in_mask(nd.outmask, n + slot[leg])) & 1);
             else
-              bit = int((kappa >> rank_in_mask(nd.smask, slot[leg])) & 1);
+              bit = int((kappa >> rank_in_mask(nd.smask, slot[leg] - J)) & 1);
             idx |= int64_t(bit) << (R - 1 - a);
           }
           const cplx x = nl.data[idx];
@@ -689,7 +744,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       if (!nb.pairs.empty()) put(nb.off_pairs, nb.pairs);
     }
     put(blk.off_idx, blk.idx);
+    put(blk.off_eoff, blk.eoff);
     put(blk.off_rho, blk.rho);
+    put(blk.off_slo, blk.slo);
   }
 
   // ---- stats -----------------------------------------------------------------
@@ -698,9 +755,10 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   st.n_leaves = L;
   st.n_internal = L - 1;
   st.k = k;
-  st.k_distinct = kd;
+  st.k_distinct = kdr;
   st.n_qubits = n;
   st.n_sliced = s;
+  st.n_stacked = J;
   st.n_blocks = int64_t(p.blocks.size());
   for (int T = 0; T < nn; ++T)
     st.max_tensor_elems = std::max<int64_t>(st.max_tensor_elems, p.nodes[T].size());
@@ -716,7 +774,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       // A node without output legs keeps its table across blocks when it
       // depends on no slice bit.
       const bool kept = nd.outmask == 0 && nd.smask == 0 && &blk != &p.blocks.front();
-      const double ev = kept ? 0.0 : evals_over_all_slices(nd.smask, s);
+      const double ev = kept ? 0.0 : evals_over_all_slices(nd.smask, s - J);
       st.cmacs_per_slice += cm;
       st.cmacs_full += ev * cm;
       st.rw_elems_full += ev * (double(nv(nd.left)) * p.nodes[nd.left].size() +
@@ -862,7 +920,9 @@ int64_t nvar_in(const Plan* p, const Block& blk, int id) {
   return p->nodes[id].leaf ? p->nodes[id].leaf_nvar : blk.nodes[id - p->n_leaves].nvar;
 }
 
-double evals_per_call(const Plan* p, int T) { return evals_over_all_slices(p->nodes[T].smask, p->s); }
+double evals_per_call(const Plan* p, int T) {
+  return evals_over_all_slices(p->nodes[T].smask, p->s - p->sj);
+}
 
 ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
   char* ws = static_cast<char*>(p->ws);
@@ -944,9 +1004,14 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
   const uint64_t amax_words = uint64_t(kAmaxSlots) * kAmaxStride;
   if (fp16) launch_zero(ws + p->off_amax, uint64_t(p->nodes.size()) * amax_words * 8, stream);
   const int L = p->n_leaves;
+  // Steps of 2^sj consecutive slices: step c covers slices [c 2^sj, (c + 1) 2^sj)
+  // with its low slice keys in the tables' keys; the accumulation keeps the
+  // slices inside [b, e).
+  const int J = p->sj;
+  const int64_t c_begin = b >> J, c_end = ((e - 1) >> J) + 1;
   for (int bi = 0; bi < int(p->blocks.size()); ++bi) {
     const Block& blk = p->blocks[bi];
-    for (int64_t sigma = b; sigma < e; ++sigma) {
+    for (int64_t sigma = c_begin; sigma < c_end; ++sigma) {
       for (int T = L; T < int(p->nodes.size()); ++T) {
         Node& nd = p->nodes[T];
         const NodeBlock& nb = blk.nodes[T - L];
@@ -979,13 +1044,16 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
         nd.cur_key = key;
         nd.cur_block = bi;
       }
-      const int64_t nk = int64_t(blk.idx.size());
-      const double acc_bytes = double(nk) * (8.0 + 8.0 + 2 * 16.0 + 2 * 16.0);
+      const int64_t ng = int64_t(blk.idx.size());
+      const double acc_bytes = double(ng) * (4.0 + 8.0 + 2 * 16.0 + 2 * 16.0) +
+                               double(blk.rho.size()) * (8.0 + 8.0);
       timed(p, stream, XEB_KERNEL_ACCUMULATE, -1, 0.0, acc_bytes, [&] {
         launch_accumulate(node_ptr(p, p->root, sigma),
                           reinterpret_cast<const int32_t*>(ws + blk.off_idx),
+                          reinterpret_cast<const int32_t*>(ws + blk.off_eoff),
                           reinterpret_cast<const int32_t*>(ws + blk.off_rho),
-                          static_cast<double2*>(amps), comp, nk, stream);
+                          reinterpret_cast<const int32_t*>(ws + blk.off_slo), sigma << J, b, e,
+                          static_cast<double2*>(amps), comp, ng, stream);
       });
       hip_check(hipGetLastError(), "accumulate launch");
     }

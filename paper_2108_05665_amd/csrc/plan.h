@@ -30,13 +30,20 @@ struct NodeBlock {
   uint64_t off_lidx = 0, off_ridx = 0, off_pairs = 0;
 };
 
-// A contiguous range of the distinct strings in lexicographic tuple order.
+// A contiguous range of the distinct keyed strings (string, low slice key) in
+// lexicographic tuple order.
 struct Block {
   int64_t first = 0, count = 0;
   std::vector<NodeBlock> nodes;  // indexed by internal node id - n_leaves
-  std::vector<int32_t> idx;      // positions (in the caller's list) of its strings
-  std::vector<int32_t> rho;      // root key of each of them
-  uint64_t off_idx = 0, off_rho = 0;
+  // Slice accumulation: one entry group per caller position that has keyed
+  // strings in this block: idx[g] is the position (in the caller's list),
+  // entries eoff[g] .. eoff[g + 1] - 1 its keyed strings in increasing low
+  // slice key slo, each with its root key rho.
+  std::vector<int32_t> idx;
+  std::vector<int32_t> eoff;
+  std::vector<int32_t> rho;
+  std::vector<int32_t> slo;
+  uint64_t off_idx = 0, off_eoff = 0, off_rho = 0, off_slo = 0;
 };
 
 // A node of the contraction tree (leaf or internal).
@@ -46,8 +53,12 @@ struct Node {
   // Tensor legs (internal, unsliced), in layout order: position p of this list
   // is bit p of the element index inside one key's tensor.
   std::vector<int32_t> legs;
-  uint64_t outmask = 0;  // qubits whose output leg lies in this subtree
-  uint64_t smask = 0;    // slice-id bits whose leg lies in this subtree
+  // Key bits whose leg lies in this subtree: qubit q (bit q < n) or stacked
+  // slice-id bit j (bit n + j, j < sj).
+  uint64_t outmask = 0;
+  // Looped slice-id bits whose leg lies in this subtree: bit j is slice-id
+  // bit sj + j.
+  uint64_t smask = 0;
   // Leaf only: keys over all strings (pext of the string on outmask).
   int64_t leaf_nvar = 1;
   std::vector<uint64_t> leaf_keys;
@@ -81,6 +92,7 @@ struct Plan {
   xeb_options_t opt{};
   int n_qubits = 0;
   int s = 0;
+  int sj = 0;  // stacked low slice bits (xeb_options_t::stack_slices)
   std::vector<int32_t> sliced;
   int64_t k = 0, kd = 0;
   int n_leaves = 0;

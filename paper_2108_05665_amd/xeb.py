@@ -70,6 +70,7 @@ class Options(ctypes.Structure):
         ("force_generic", ctypes.c_int32),
         ("max_ksplit", ctypes.c_int32),
         ("mfma_min_cmacs", ctypes.c_double),
+        ("stack_slices", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ class Stats(ctypes.Structure):
         ("evals_full", ctypes.c_double),
         ("workspace_bytes", ctypes.c_uint64),
         ("n_blocks", ctypes.c_int64),
+        ("n_stacked", ctypes.c_int32),
     ]
 
 
@@ -228,7 +230,8 @@ class Plan:
 
     def __init__(self, circ, bitstrings, tree_children, sliced_legs=(), *, fuse_1q=True,
                  fold_kets=True, precision="c64", device=None, memory_budget=0, trace=0,
-                 force_generic=False, max_ksplit=0, mfma_min_cmacs=0.0, bind=True):
+                 force_generic=False, max_ksplit=0, mfma_min_cmacs=0.0, stack_slices=0,
+                 bind=True):
         self._h = _P()
         c, keep = _circuit_struct(circ)
         bs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
@@ -247,6 +250,7 @@ class Plan:
         o.force_generic = int(force_generic)
         o.max_ksplit = int(max_ksplit)
         o.mfma_min_cmacs = float(mfma_min_cmacs)
+        o.stack_slices = int(stack_slices)
         _check(_lib.xeb_plan_create(ctypes.byref(c), bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                     bs.size, ctypes.byref(tree),
                                     sl.ctypes.data_as(_I32P) if sl.size else None, sl.size,

@@ -109,6 +109,38 @@ def test_plan_counts_all_strings():
         assert ns["variants"] == 2 ** nout
 
 
+@pytest.mark.parametrize("J", [0, 2, 4])
+def test_stacked_slice_counts_closed_form(J):
+    """Stacked slices (stack_slices = J): every string meets every low slice
+    key, so a node's keys are its string keys (counted by brute force in the
+    oracle) times 2^(stacked sliced legs on its leaves); a node is evaluated
+    once per change of its looped slice bits (slices in increasing order,
+    2^J per step)."""
+    c = grid_circuit(3, 4, 7, 90 + J)
+    s = prefix_bitstrings(12, 150, 5, 91)
+    ch, sl, _ = planner.plan(c, s, n_sliced=5, trials=3)
+    p = xeb.Plan(c, s, ch, sl, stack_slices=J, bind=False)
+    net = build_network(c)
+    tree = memo.Tree(len(net.leaves), ch)
+    want = memo.distinct_key_counts(net, tree, s)
+    st = p.stats()
+    assert st["n_stacked"] == J and st["n_sliced"] == len(sl)
+    evals = 0.0
+    for ns in p.all_node_stats():
+        legs = {l for j in tree.leaves_dfs(ns["node"]) for l in net.leaves[j].legs}
+        mask = sum(1 << j for j, leg in enumerate(sl) if leg in legs)
+        assert ns["slice_mask"] == mask
+        low = bin(mask & ((1 << J) - 1)).count("1")
+        assert ns["variants"] == want[ns["node"]] << low
+        hi = mask >> J
+        evals += 1.0 if hi == 0 else 2.0 ** (len(sl) - J - ((hi & -hi).bit_length() - 1))
+    assert st["evals_full"] == evals
+    assert st["sum_variants"] == sum(ns["variants"] for ns in p.all_node_stats())
+    with pytest.raises(xeb.XebError) as e:
+        xeb.Plan(c, s, ch, sl, stack_slices=len(sl) + 1, bind=False)
+    assert e.value.code == xeb.XEB_EINVAL
+
+
 def test_plan_rejects_bad_inputs():
     c = grid_circuit(2, 3, 4, 80)
     s = uniform_bitstrings(6, 10, 81)
