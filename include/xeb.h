@@ -273,6 +273,26 @@ int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* 
  */
 int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F);
 
+/*
+ * Linear XEB without a plan and without any allocation, for callers that
+ * cannot allocate device memory: code running under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same reduction, order and
+ * result as xeb_fidelity (bit for bit, for the same amps and k).
+ *   amps (device, current device) complex128 [k]; 1 <= k <= XEB_NOALLOC_MAX_STRINGS.
+ *   n_qubits: n of Eq. (1), 1 <= n <= 64.
+ *   F (device) one double, written on `stream`; the call neither waits for the
+ *     stream nor copies to the host.
+ * The chunk partials live in an array the library keeps on each device for
+ * the life of the process (1 MiB, XEB_NOALLOC_MAX_STRINGS / 4096 slots, taken
+ * on the device's first call); the call allocates nothing and frees nothing.
+ * Every call on one device shares that array: calls that overlap on a device
+ * (concurrent streams or threads) race; serialize them.
+ * Errors: XEB_EINVAL (k == 0, NULL pointer, n out of range), XEB_ELIMIT
+ * (k above the limit), XEB_EHIP.
+ */
+#define XEB_NOALLOC_MAX_STRINGS (((int64_t)1) << 28)
+int xeb_fidelity_noalloc(const void* amps, int64_t k, int32_t n_qubits, double* F, void* stream);
+
 /* Plan-wide figures (cost measures of Appendix A/C with exact variant counts). */
 int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats);
 

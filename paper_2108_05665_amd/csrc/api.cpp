@@ -165,6 +165,15 @@ int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F) {
   });
 }
 
+static_assert(XEB_NOALLOC_MAX_STRINGS == xeb::kXebStaticMaxStrings, "allocation-free XEB limit");
+
+int xeb_fidelity_noalloc(const void* amps, int64_t k, int32_t n_qubits, double* F, void* stream) {
+  return guarded([&] {
+    xeb::launch_xeb_static(static_cast<const double2*>(amps), k, n_qubits, F,
+                           static_cast<hipStream_t>(stream));
+  });
+}
+
 int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats) {
   return guarded([&] {
     if (!stats) xeb::fail(XEB_EINVAL, "stats is NULL");

@@ -14,6 +14,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "compensated.h"
 #include "plan.h"
 
@@ -74,6 +77,36 @@ __global__ void __launch_bounds__(kXebFinalThreads) k_xeb_final(const double2* p
 
 }  // namespace
 
+// Both passes: partial pairs in `partial` (groups slots), F in *out.
+void launch_xeb_into(const double2* amps, int64_t k, int n_qubits, double2* partial, double* out,
+                     hipStream_t s) {
+  const int64_t groups = (k + kXebChunk - 1) / kXebChunk;
+  k_xeb_partial<<<dim3(unsigned(groups)), dim3(kXebThreads), 0, s>>>(amps, k, partial);
+  k_xeb_final<<<dim3(1), dim3(kXebFinalThreads), 0, s>>>(partial, groups, k, n_qubits, out);
+}
+
+// Chunk partials of the allocation-free form: one array per device for the
+// life of the process, never allocated by a call.  Host code must not use
+// this name as a device address: it takes the address that
+// hipGetSymbolAddress returns for the current device (see static_scratch).
+static __device__ __align__(256) double2 scratch[kXebStaticGroups];
+
+// Device address of `scratch` on device `dev`, looked up once per device with
+// that device current.
+double2* static_scratch(int dev) {
+  static std::mutex mu;
+  static double2* ptr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) fail(XEB_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) fail(XEB_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    ptr[dev] = static_cast<double2*>(p);
+  }
+  return ptr[dev];
+}
+
 uint64_t xeb_scratch_bytes(int64_t k) {
   const int64_t groups = k > 0 ? (k + kXebChunk - 1) / kXebChunk : 0;
   return uint64_t(1 + groups) * 16;
@@ -81,11 +114,22 @@ uint64_t xeb_scratch_bytes(int64_t k) {
 
 void launch_xeb(const double2* amps, int64_t k, int n_qubits, void* scratch_dev, hipStream_t s) {
   if (k <= 0) return;
-  const int64_t groups = (k + kXebChunk - 1) / kXebChunk;
   double2* slots = static_cast<double2*>(scratch_dev);
-  k_xeb_partial<<<dim3(unsigned(groups)), dim3(kXebThreads), 0, s>>>(amps, k, slots + 1);
-  k_xeb_final<<<dim3(1), dim3(kXebFinalThreads), 0, s>>>(slots + 1, groups, k, n_qubits,
-                                                        reinterpret_cast<double*>(slots));
+  launch_xeb_into(amps, k, n_qubits, slots + 1, reinterpret_cast<double*>(slots), s);
+}
+
+void launch_xeb_static(const double2* amps, int64_t k, int n_qubits, double* F_dev, hipStream_t s) {
+  if (k <= 0) fail(XEB_EINVAL, "XEB of an empty batch");
+  if (k > kXebStaticMaxStrings)
+    fail(XEB_ELIMIT, "k = " + std::to_string(k) + " exceeds the allocation-free limit of " +
+                         std::to_string(kXebStaticMaxStrings) + " strings");
+  if (n_qubits < 1 || n_qubits > 64) fail(XEB_EINVAL, "n_qubits must be in [1, 64]");
+  if (!amps || !F_dev) fail(XEB_EINVAL, "amps or F is NULL");
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  double2* partial = static_scratch(dev);
+  launch_xeb_into(amps, k, n_qubits, partial, F_dev, s);
+  hip_check(hipGetLastError(), "xeb launch");
 }
 
 }  // namespace xeb

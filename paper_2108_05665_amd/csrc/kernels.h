@@ -117,5 +117,14 @@ void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hip
 constexpr int64_t kXebChunk = 4096;
 uint64_t xeb_scratch_bytes(int64_t k);
 void launch_xeb(const double2* amps, int64_t k, int n_qubits, void* scratch, hipStream_t s);
+// The same reduction with its chunk partials in a per-device array that the
+// library holds for the life of the process (no allocation, no workspace):
+// at most kXebStaticGroups chunks, i.e. kXebStaticMaxStrings strings; F goes
+// to F_dev (device).  Runs on the current device.  Calls that overlap on one
+// device share the array and race.
+constexpr int64_t kXebStaticGroups = int64_t(1) << 16;  // 1 MiB of partial pairs
+constexpr int64_t kXebStaticMaxStrings = kXebStaticGroups * kXebChunk;
+constexpr int kMaxDevices = 64;
+void launch_xeb_static(const double2* amps, int64_t k, int n_qubits, double* F_dev, hipStream_t s);
 
 }  // namespace xeb

@@ -164,6 +164,7 @@ _SIG = {
     "xeb_plan_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "xeb_contract": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "xeb_fidelity": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "xeb_fidelity_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     "xeb_plan_autotune": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(AutotuneReport)]),
     "xeb_plan_get_node_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeConfig)]),
     "xeb_plan_set_node_config": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(NodeConfig)]),
@@ -222,6 +223,26 @@ def network_describe(circ, fuse_1q: bool = True, fold_kets: bool = True):
                                      lq.ctypes.data_as(_I32P)))
     leaves = [legs[offs[j]:offs[j + 1]].tolist() for j in range(nl.value)]
     return leaves, ng.value, lq[: ng.value].tolist()
+
+
+NOALLOC_MAX_STRINGS = 1 << 28
+
+
+def fidelity_noalloc(amps, n_qubits: int, out, stream=None):
+    """xeb_fidelity_noalloc: linear XEB of a device complex128 tensor `amps`
+    into the one-element device float64 tensor `out`, enqueued on `stream`
+    (torch's current stream by default); returns `out` without waiting."""
+    import torch
+
+    if amps.dtype != torch.complex128 or not amps.is_cuda or not amps.is_contiguous():
+        raise ValueError("amps must be a contiguous complex128 CUDA tensor")
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1:
+        raise ValueError("out must be a float64 CUDA tensor with one element")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(_lib.xeb_fidelity_noalloc(ctypes.c_void_p(amps.data_ptr()), amps.numel(), int(n_qubits),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 class Plan:
