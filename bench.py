@@ -358,6 +358,19 @@ def main() -> int:
         eager_step()
         torch.cuda.synchronize()
         prof = {name: plan.read_profile(name) for name in ("mfma", "generic", "accumulate", "splitk")}
+        nodes = []
+        for ns in plan.all_node_stats():
+            np_ = plan.read_node_profile(ns["node"])
+            if np_["launches"] == 0 or np_["seconds"] <= 0:
+                continue
+            nodes.append({"node": ns["node"], "kernel": ns["kernel"], "tile": ns["tile"],
+                          "swapped": ns["swapped"], "pair_mode": ns["pair_mode"],
+                          "ksplit": ns["ksplit"], "keys": ns["variants"],
+                          "m_k_n_bits": [ns["m_bits"], ns["k_bits"], ns["n_bits"]],
+                          "launches": np_["launches"], "seconds": np_["seconds"],
+                          "algorithmic_tflops": 8.0 * np_["cmacs"] / np_["seconds"] / 1e12,
+                          "gbs": np_["bytes"] / np_["seconds"] / 1e9})
+        nodes.sort(key=lambda x: -x["seconds"])
         plan.set_profiling(False)
         # Full amplitudes of the timed graph form against the stored FP64
         # oracle values (first 64 strings, all slices summed).
@@ -365,7 +378,7 @@ def main() -> int:
         sec = sec_eager if sec_graph is None else sec_graph
         results[prec] = dict(
             sec=sec, sec_eager=sec_eager, F=F, amps=final, prof=prof, st=st, t_plan=t_plan,
-            t_capture=t_capture, oracle=oerr, tune=tune,
+            t_capture=t_capture, oracle=oerr, tune=tune, top_nodes=nodes[:12],
             graph_vs_eager_max_abs=float(np.max(np.abs(final - eager_amps))) if len(final) else 0.0,
             F_eager=F_eager, amps_per_s=len(strings) / sec,
             useful_tflops=8.0 * st["cmacs_full"] / sec / 1e12,
@@ -406,6 +419,12 @@ def main() -> int:
             "xeb": x["F"], "oracle_check": x["oracle"],
             "err_bound": ERR_BOUND[prec], "kernel_time_share": x["share"],
             "roofline": roofline(x["prof"], prec), "plan_compile_s": x["t_plan"],
+            "generic_kernel": {
+                "gbs": x["prof"]["generic"]["bytes"] / max(x["prof"]["generic"]["seconds"], 1e-30) / 1e9,
+                "hbm_frac": x["prof"]["generic"]["bytes"] / max(x["prof"]["generic"]["seconds"], 1e-30)
+                            / (HBM_PEAK_GBS * 1e9),
+                "launches": x["prof"]["generic"]["launches"], "seconds": x["prof"]["generic"]["seconds"]},
+            "top_nodes": x["top_nodes"],
             **compare.get(prec, {}),
         }
         for prec, x in results.items()

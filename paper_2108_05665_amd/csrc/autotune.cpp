@@ -75,7 +75,8 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   for (int sw = 0; sw < 2; ++sw) {
     const double rows = double(sw ? nr : nl) * std::ldexp(1.0, sw ? nd.nb : nd.mb);
     const double cols = double(sw ? nl : nr) * std::ldexp(1.0, sw ? nd.mb : nd.nb);
-    for (int tile = 0; tile < 3; ++tile) {
+    for (int tile = 0; tile < kMfmaTiles; ++tile) {
+      if (tile == 3) continue;
       int bm = 0, bn = 0;
       mfma_tile_shape(tile, &bm, &bn);
       const double padded = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *

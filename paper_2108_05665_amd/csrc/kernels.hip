@@ -247,6 +247,9 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //   1: 32 x 128, waves 1 x 4, one 32 x 32 block each
 //   2: 16 x 256, waves 1 x 4, four 16 x 16 blocks each
 //   3: 64 x 16,  waves 4 x 1, one 16 x 16 block each (narrow keyed products)
+//   4: 128 x 128, waves 2 x 2, four 32 x 32 blocks each (each operand
+//      fragment read from LDS feeds two blocks: half the LDS reads and half
+//      the operand re-fetch of the 64 x 64 tile per MFMA)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -286,6 +289,8 @@ template <>
 struct Tile<2> { static constexpr int BM = 16, BN = 256, MF = 16, WM = 1; };
 template <>
 struct Tile<3> { static constexpr int BM = 64, BN = 16, MF = 16, WM = 4; };
+template <>
+struct Tile<4> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 2; };
 
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
@@ -308,7 +313,7 @@ struct TileInfo {
   static constexpr int LDS_MAIN = LDS_A + LDS_B;
   static constexpr int LDS_EPI = BM * (BN + 1) * 2;
   static constexpr int LDS = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
-  static constexpr int LOG_BM = BM == 64 ? 6 : (BM == 32 ? 5 : 4);
+  static constexpr int LOG_BM = BM == 128 ? 7 : (BM == 64 ? 6 : (BM == 32 ? 5 : 4));
   static constexpr int LOG_BN = BN == 16 ? 4 : (BN == 64 ? 6 : (BN == 128 ? 7 : 8));
   static constexpr int UBITS = LOG_BM + LOG_BN;
   static constexpr int PER_THREAD = BM * BN / 256;
@@ -769,10 +774,11 @@ __global__ void __launch_bounds__(256 * KG) k_contract_mfma(ContractArgs g) {
 // Split FP16 / BF16 contraction.  Same walk, tiles, K groups, split K and
 // epilogue as k_contract_mfma; the operands are staged in LDS as four planes
 // per operand (hi re, hi im, lo re, lo im; rows of TK + 8 halves), so that
-//   re = sum ar.br - sum ai.bi,   im = sum ar.bi + sum ai.br
-// take the planes as they are: the real part keeps two accumulators (ar.br
-// and ai.bi, subtracted at the end) and no operand needs a sign flip or a
-// swap of its (re, im) halves.  Each product is hi.hi + hi.lo + lo.hi.
+//   re = sum ar.br + ai.(-bi),   im = sum ar.bi + ai.br
+// take the planes as they are, except that the column operand's imaginary
+// fragments are negated for the real part (one sign-bit XOR per packed pair
+// in registers): two accumulators per 32 x 32 block.  Each product is
+// hi.hi + hi.lo + lo.hi.
 // A thread stages pairs of float4 (four consecutive complex of one row), and
 // addresses inside a tile are 32-bit byte offsets from the tile's first row;
 // rows past the operand's end re-read its last row (their results are never
@@ -894,15 +900,14 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
     const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
     const int64_t pn = next_p(p);
 
-    accv acc_rr[T::FM][T::FN], acc_ii[T::FM][T::FN], acc_im[T::FM][T::FN];
+    accv acc_re[T::FM][T::FN], acc_im[T::FM][T::FN];
 #pragma unroll
     for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < T::FN; ++fn)
 #pragma unroll
         for (int v = 0; v < T::REGS; ++v) {
-          acc_rr[fm][fn][v] = 0.f;
-          acc_ii[fm][fn][v] = 0.f;
+          acc_re[fm][fn][v] = 0.f;
           acc_im[fm][fn][v] = 0.f;
         }
 
@@ -944,20 +949,22 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
           const u32x4 bih = *reinterpret_cast<const u32x4*>(b + PL_B);
           const u32x4 brl = *reinterpret_cast<const u32x4*>(b + 2 * PL_B);
           const u32x4 bil = *reinterpret_cast<const u32x4*>(b + 3 * PL_B);
+          // -bi: the sign bit of both packed halves (FP16 and BF16 alike).
+          const u32x4 nbih = bih ^ 0x80008000u, nbil = bil ^ 0x80008000u;
 #pragma unroll
           for (int fm = 0; fm < T::FM; ++fm) {
 #define XEB_MMA(acc, x, y) acc = mma_split<MF, PREC>(x, y, acc)
-            XEB_MMA(acc_rr[fm][fn], arh[fm], brh);
-            XEB_MMA(acc_ii[fm][fn], aih[fm], bih);
+            XEB_MMA(acc_re[fm][fn], arh[fm], brh);
             XEB_MMA(acc_im[fm][fn], arh[fm], bih);
-            XEB_MMA(acc_rr[fm][fn], arh[fm], brl);
-            XEB_MMA(acc_ii[fm][fn], aih[fm], bil);
+            XEB_MMA(acc_re[fm][fn], aih[fm], nbih);
             XEB_MMA(acc_im[fm][fn], aih[fm], brh);
-            XEB_MMA(acc_rr[fm][fn], arl[fm], brh);
-            XEB_MMA(acc_ii[fm][fn], ail[fm], bih);
+            XEB_MMA(acc_re[fm][fn], arh[fm], brl);
             XEB_MMA(acc_im[fm][fn], arh[fm], bil);
-            XEB_MMA(acc_im[fm][fn], arl[fm], bih);
+            XEB_MMA(acc_re[fm][fn], aih[fm], nbil);
             XEB_MMA(acc_im[fm][fn], aih[fm], brl);
+            XEB_MMA(acc_re[fm][fn], arl[fm], brh);
+            XEB_MMA(acc_im[fm][fn], arl[fm], bih);
+            XEB_MMA(acc_re[fm][fn], ail[fm], nbih);
             XEB_MMA(acc_im[fm][fn], ail[fm], brh);
 #undef XEB_MMA
           }
@@ -981,8 +988,7 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
               r = wm * T::BMW + fm * 16 + 4 * (lane >> 4) + v;
               c = wn * T::BNW + fn * 16 + (lane & 15);
             }
-            f(r, c, make_float2((acc_rr[fm][fn][v] - acc_ii[fm][fn][v]) * s_out,
-                                acc_im[fm][fn][v] * s_out));
+            f(r, c, make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out));
           }
     };
     if constexpr (KG == 2) {
@@ -1244,6 +1250,8 @@ void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t ro
       }
     }
     launch_cfg<1, PREC, lo>(a, s, rowsA, rowsB);
+  } else if (a.tile == 4) {
+    launch_cfg<4, PREC, lo>(a, s, rowsA, rowsB);
   } else {
     if (a.tile == 3)
       launch_cfg<3, PREC, lo>(a, s, rowsA, rowsB);
@@ -1288,14 +1296,16 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
     launch_reduce_cfg<1>(a, s, rowsA, rowsB);
   else if (a.tile == 2)
     launch_reduce_cfg<2>(a, s, rowsA, rowsB);
-  else
+  else if (a.tile == 3)
     launch_reduce_cfg<3>(a, s, rowsA, rowsB);
+  else
+    launch_reduce_cfg<4>(a, s, rowsA, rowsB);
 }
 
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
   if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
-  if (tk == lo) return tile >= 0 && tile <= 3;
+  if (tk == lo) return tile >= 0 && tile <= 4;
   if (tk == 2 * lo) return tile == 0 || (prec == 0 && tile == 1);
   return false;
 }
@@ -1306,25 +1316,25 @@ void prepare_mfma_launch(int prec) {
   if (prec == 0) {
     (void)persistent_grid<0, 0, 16, 1>(1), (void)persistent_grid<1, 0, 16, 1>(1);
     (void)persistent_grid<2, 0, 16, 1>(1), (void)persistent_grid<0, 0, 32, 1>(1);
-    (void)persistent_grid<3, 0, 16, 1>(1);
+    (void)persistent_grid<3, 0, 16, 1>(1), (void)persistent_grid<4, 0, 16, 1>(1);
     (void)persistent_grid<1, 0, 32, 1>(1), (void)persistent_grid<0, 0, 16, 2>(1);
     (void)persistent_grid<0, 0, 32, 2>(1);
   } else if (prec == 1) {
     (void)persistent_grid<0, 1, 32, 1>(1), (void)persistent_grid<1, 1, 32, 1>(1);
     (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
-    (void)persistent_grid<3, 1, 32, 1>(1);
+    (void)persistent_grid<3, 1, 32, 1>(1), (void)persistent_grid<4, 1, 32, 1>(1);
     (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
     (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
     (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
-    (void)persistent_grid<3, 2, 32, 1>(1);
+    (void)persistent_grid<3, 2, 32, 1>(1), (void)persistent_grid<4, 2, 32, 1>(1);
     (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  static const int kBM[4] = {64, 32, 16, 64}, kBN[4] = {64, 128, 256, 16};
-  const int t = tile >= 0 && tile < 4 ? tile : 0;
+  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128}, kBN[kMfmaTiles] = {64, 128, 256, 16, 128};
+  const int t = tile >= 0 && tile < kMfmaTiles ? tile : 0;
   *bm = kBM[t];
   *bn = kBN[t];
 }

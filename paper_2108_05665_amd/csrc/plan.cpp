@@ -646,7 +646,10 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
         const int64_t nr = p.nodes[nd.right].leaf ? p.nodes[nd.right].leaf_nvar : blk.nodes[nd.right - L].nvar;
         if (nd.kb >= 7 && mfma_capable(nd, nl, nr, nb)) long_k = true;
       }
-    if (long_k) partial = std::max<uint64_t>(partial, kTunePartialBytes);
+    // (Under a memory budget the reserve takes at most 1/16 of it.)
+    const uint64_t reserve =
+        o.memory_budget ? std::min<uint64_t>(kTunePartialBytes, o.memory_budget / 16) : kTunePartialBytes;
+    if (long_k) partial = std::max<uint64_t>(partial, reserve);
     p.off_partial = off;
     p.partial_bytes = align_up(partial);
     off += p.partial_bytes;

@@ -326,3 +326,68 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
                                              seconds=sec, trial=info0["trial"], anneal_restart=r,
                                              table_bytes=ainfo["table_bytes"]))
     return best[1], best[2], best[3]
+
+
+def choose_slicing(circ, bitstrings, memory_budget: int, max_sliced: int = 40, stack: bool = True,
+                   precision: str = "c64", trials: int = 8, seed: int = 0, anneal_steps: int = 0,
+                   anneal_restarts: int = 4, workers: int = 1, fuse_1q: bool = True,
+                   fold_kets: bool = True):
+    """The emulation-mode planner (Appendix C: run the memory bookkeeping
+    without the tensors): the smallest number of sliced legs s whose plan fits
+    `memory_budget` bytes of device workspace, decided by the plan compiler's
+    exact host dry run (xeb_plan_create without a device), then the largest
+    number of stacked slice bits J <= s that still fits.
+
+    For s = 0, 1, 2, ... the tree and slices come from `plan` (the table
+    budget steering the optimizer when anneal_steps > 0); a plan fits when
+    the dry run's workspace, after cutting the strings into blocks if it
+    must, is within the budget.  Stacking stops short of the J that would
+    need more string blocks than the unstacked plan.  Returns a dict with
+    the tree (`children`),
+    `sliced` legs, `stack_slices`, the dry run's `workspace_bytes` and
+    `n_blocks`, the planner's `info`, and `tried`: one record per s tried,
+    each with the workspace it needed (None when no block count fits)."""
+    tried = []
+    for s in range(0, max_sliced + 1):
+        ch, sl, info = plan(circ, bitstrings, n_sliced=s, trials=trials, seed=seed,
+                            fuse_1q=fuse_1q, fold_kets=fold_kets, anneal_steps=anneal_steps,
+                            anneal_restarts=anneal_restarts, workers=workers,
+                            table_bytes_max=memory_budget if anneal_steps > 0 else None)
+        if len(sl) < s:  # no leg left to slice
+            break
+        need = None
+        try:
+            p = _xeb.Plan(circ, bitstrings, ch, sl, fuse_1q=fuse_1q, fold_kets=fold_kets,
+                          precision=precision, memory_budget=memory_budget, bind=False)
+            st = p.stats()
+            need = int(st["workspace_bytes"])
+            p.close()
+        except _xeb.XebError as e:
+            if e.code != _xeb.XEB_ENOMEM:
+                raise
+        tried.append({"s": s, "workspace_bytes": need})
+        if need is None:
+            continue
+        best = {"children": ch, "sliced": sl, "stack_slices": 0, "workspace_bytes": need,
+                "n_blocks": int(st["n_blocks"]), "info": info, "tried": tried}
+        if stack:
+            for J in range(len(sl), 0, -1):
+                if circ.n_qubits + J > 64:
+                    continue
+                try:
+                    p = _xeb.Plan(circ, bitstrings, ch, sl, fuse_1q=fuse_1q, fold_kets=fold_kets,
+                                  precision=precision, memory_budget=memory_budget,
+                                  stack_slices=J, bind=False)
+                except _xeb.XebError as e:
+                    if e.code != _xeb.XEB_ENOMEM:
+                        raise
+                    continue
+                st = p.stats()
+                p.close()
+                if int(st["n_blocks"]) > best["n_blocks"]:
+                    continue
+                best.update(stack_slices=J, workspace_bytes=int(st["workspace_bytes"]),
+                            n_blocks=int(st["n_blocks"]))
+                break
+        return best
+    raise ValueError(f"no slicing up to {max_sliced} legs fits {memory_budget} bytes")

@@ -276,8 +276,9 @@ def test_node_config_get_set_and_validation():
     assert (got["tile"], got["swapped"], got["k_slab"], got["k_groups"]) == (0, 1 - before["swapped"], 32, 2)
     ns = {x["node"]: x for x in p.all_node_stats()}[node]
     assert (ns["k_slab"], ns["k_groups"]) == (32, 2)
-    for bad in (dict(tile=4), dict(k_slab=64), dict(k_groups=3), dict(tile=2, k_groups=2),
-                dict(tile=3, k_groups=2), dict(tile=3, k_slab=32),
+    for bad in (dict(tile=5), dict(tile=-1), dict(k_slab=64), dict(k_groups=3), dict(tile=2, k_groups=2),
+                dict(tile=3, k_groups=2), dict(tile=3, k_slab=32), dict(tile=4, k_slab=32),
+                dict(tile=4, k_groups=2),
                 dict(ksplit=3), dict(ksplit=1 << 7)):
         args = dict(tile=0, swapped=0, ksplit=1, k_slab=16, k_groups=1)
         args.update(bad)
@@ -399,3 +400,27 @@ def test_sparse_batch_nodes_default_to_the_keyed_form():
             best = min(x for x in (pad(t, w) for t in shapes for w in (0, 1)) if x is not None)
             assert got == best
     assert seen >= 4
+
+
+@pytest.mark.parametrize("budget", [2 << 20, 512 << 10])
+def test_choose_slicing_emulation_mode(budget):
+    """The emulation-mode planner (Appendix C): the chosen plan's host dry run
+    fits the budget, every smaller slice count it tried did not, and the
+    stacked plan needs no more string blocks than the unstacked one."""
+    c = grid_circuit(4, 4, 8, 95)
+    s = uniform_bitstrings(16, 300, 96)
+    r = planner.choose_slicing(c, s, budget, trials=3)
+    ns = len(r["sliced"])
+    assert [t["s"] for t in r["tried"]] == list(range(ns + 1))
+    assert all(t["workspace_bytes"] is None for t in r["tried"][:-1])
+    p = xeb.Plan(c, s, r["children"], r["sliced"], memory_budget=budget,
+                 stack_slices=r["stack_slices"], bind=False)
+    assert p.workspace_bytes() == r["workspace_bytes"] <= budget
+    assert p.stats()["n_blocks"] == r["n_blocks"]
+    flat = xeb.Plan(c, s, r["children"], r["sliced"], memory_budget=budget, bind=False)
+    assert r["n_blocks"] <= flat.stats()["n_blocks"]
+    if ns:
+        with pytest.raises(xeb.XebError) as e:
+            ch, sl, _ = planner.plan(c, s, n_sliced=ns - 1, trials=3)
+            xeb.Plan(c, s, ch, sl, memory_budget=budget, bind=False)
+        assert e.value.code == xeb.XEB_ENOMEM

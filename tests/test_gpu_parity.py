@@ -445,6 +445,48 @@ def test_every_mfma_variant_vs_state_vector(precision):
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_fp16", "split_bf16"])
+def test_wide_tile_vs_state_vector(precision):
+    """The 128x128 tile (four 32x32 blocks per wave) forced on every
+    MFMA-capable node, unsplit, with split K, and in the keyed form where a
+    key's product spans at least 64 x 64: amplitudes within the bound of the
+    state vector, reruns bit-identical."""
+    tol = AMP_TOL if precision == "c64" else SPLIT_TOL
+    circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
+    strings = prefix_bitstrings(20, 4000, 12, 5)
+    ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
+    ref = statevec.state_vector(circ)[strings.astype(np.int64)]
+    lo = 16 if precision == "c64" else 32
+    p = xeb.Plan(circ, strings, ch, sl, precision=precision, stack_slices=1, **SMALL_MFMA)
+    nodes = [ns for ns in p.all_node_stats() if ns["kernel"] == "mfma"]
+    assert nodes
+    for mode in ("plain", "split_k", "keyed"):
+        used = 0
+        for ns in nodes:
+            K = 1 << ns["k_bits"]
+            ks, keyed = 1, 0
+            if mode == "split_k" and K >= 2 * max(lo, 64):
+                ks = 2
+            if mode == "keyed":
+                rb, cb = (ns["n_bits"], ns["m_bits"]) if ns["swapped"] else (ns["m_bits"], ns["n_bits"])
+                keyed = 1 if rb >= 6 and cb >= 6 else 0
+            try:
+                p.set_node_config(ns["node"], "mfma", tile=4, swapped=ns["swapped"], ksplit=ks,
+                                  k_slab=lo, k_groups=1, keyed=keyed)
+            except xeb.XebError:
+                continue
+            used += (mode == "plain") or ks > 1 or keyed
+        a = p.new_amps()
+        p.contract(a)
+        b = p.new_amps()
+        p.contract(b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        err = _rel(a.cpu().numpy(), ref)
+        assert err <= tol, (mode, err)
+        assert used > 0, mode
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_fp16", "split_bf16"])
 @pytest.mark.parametrize("shapes", [((0, 64, 64), (1, 32, 128), (2, 16, 256)), ((3, 64, 16),),
                                     ((0, 32, 32), (3, 32, 8))],
                          ids=["wide_tiles", "narrow_tile", "part_filled_tiles"])
