@@ -158,7 +158,8 @@ typedef struct {
   int32_t kernel;            /* XEB_KERNEL_* (first block) */
   int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
   int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256, 3 = 64x16,
-                                4 = 128x128 */
+                                4 = 128x128, 5 = 128x128 on eight waves with double-
+                                buffered LDS (split forms) */
   int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
   int32_t k_slab;            /* MFMA: complex K values staged per LDS step */
   int32_t k_groups;          /* MFMA: groups of four waves splitting K inside a workgroup */
@@ -358,10 +359,11 @@ int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_
  * A node's kernel configuration (as reported by xeb_plan_node_stats), for
  * reading the autotuner's choices and applying them, or any valid
  * configuration, to a plan with the same tree.  kernel: XEB_KERNEL_GENERIC
- * (the other fields are ignored) or XEB_KERNEL_MFMA with tile 0..4, swapped
+ * (the other fields are ignored) or XEB_KERNEL_MFMA with tile 0..5, swapped
  * 0/1 (right child as the row operand), ksplit a power of two with K / ksplit
- * >= k_slab, k_slab 16 / 32 (complex64) or 32 / 64 (split forms), k_groups 1
- * or 2 (2 and the larger slab only on some tiles).  A node whose key set is
+ * >= k_slab, k_slab 16 / 32 (complex64) or 32 / 64 (split forms; 16 on tile
+ * 5, which takes no complex64), k_groups 1 or 2 (2 and the larger slab only
+ * on some tiles).  A node whose key set is
  * too sparse for the stacked product runs keyed (one GEMM per key): then
  * each key's block must cover whole tiles and ksplit must be 1.
  * xeb_plan_set_node_config applies it to every string block and fails with

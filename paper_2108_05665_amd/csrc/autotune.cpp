@@ -63,7 +63,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
     for (int sw = 0; sw < 2; ++sw)
       for (int tile = 0; tile < kMfmaTiles; ++tile) {
         if (!mfma_can_run(nd, nl, nr, nb, tile, sw, 1, 1)) continue;
-        for (int tk = lo; tk <= 2 * lo; tk *= 2)
+        for (int tk = 16; tk <= 2 * lo; tk *= 2)
           for (int kg = 1; kg <= 2; ++kg)
             if (mfma_variant_allowed(tile, p->opt.precision, tk, kg) && !(tk > lo && K < tk) &&
                 !(kg > 1 && K < 2 * tk))
@@ -84,7 +84,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
       if (16.0 * useful < padded) continue;  // mostly padding
       const int64_t tiles = node_tiles(nd, nl, nr, tile, sw);
       const int lo = mfma_default_slab(p->opt.precision);
-      for (int tk = lo; tk <= 2 * lo; tk *= 2)
+      for (int tk = 16; tk <= 2 * lo; tk *= 2)
         for (int kg = 1; kg <= 2; ++kg) {
           if (!mfma_variant_allowed(tile, p->opt.precision, tk, kg) || (tk > lo && K < tk) ||
               (kg > 1 && K < 2 * tk))

@@ -250,6 +250,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //   4: 128 x 128, waves 2 x 2, four 32 x 32 blocks each (each operand
 //      fragment read from LDS feeds two blocks: half the LDS reads and half
 //      the operand re-fetch of the 64 x 64 tile per MFMA)
+//   5: 128 x 128, eight waves with double-buffered LDS (split forms only,
+//      k_contract_split_db)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -291,6 +293,10 @@ template <>
 struct Tile<3> { static constexpr int BM = 64, BN = 16, MF = 16, WM = 4; };
 template <>
 struct Tile<4> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 2; };
+// (Tile 5, 128 x 128 with eight waves, is k_contract_split_db's own layout;
+// the entry gives its shape to the shared epilogue and tile map.)
+template <>
+struct Tile<5> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 4; };
 
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
@@ -447,20 +453,22 @@ struct TileMap {
 
 // Epilogue set-up shared by the contraction and the split-K reduction:
 // deposit tables of a tile's low row / column bits and this thread's share of
-// the write order (tile element bits 0..7 come from the thread id).
-template <int CFG>
+// the write order (tile element bits 0 .. log2(NT) - 1 come from the thread id
+// of an NT-thread workgroup).
+template <int CFG, int NT = 256>
 __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* dep_m_lo,
                                                int64_t* dep_n_lo, int& r_tid, int& c_tid) {
   using T = TileInfo<CFG, 0>;
+  constexpr int LOG_NT = NT == 512 ? 9 : 8;
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t m_lo_mask = (M < T::BM ? M : T::BM) - 1;
   const int64_t n_lo_mask = (N < T::BN ? N : T::BN) - 1;
-  for (int i = threadIdx.x; i < T::BM; i += 256) dep_m_lo[i] = deposit(i & m_lo_mask, g.mapM);
-  for (int i = threadIdx.x; i < T::BN; i += 256) dep_n_lo[i] = deposit(i & n_lo_mask, g.mapN);
+  for (int i = threadIdx.x; i < T::BM; i += NT) dep_m_lo[i] = deposit(i & m_lo_mask, g.mapM);
+  for (int i = threadIdx.x; i < T::BN; i += NT) dep_n_lo[i] = deposit(i & n_lo_mask, g.mapN);
   r_tid = 0;
   c_tid = 0;
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < LOG_NT; ++b) {
     if ((threadIdx.x >> b) & 1) {
       const int u = g.ubit[b];
       if (u < 32)
@@ -472,8 +480,9 @@ __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* d
 }
 
 // Writes a finished tile parked in LDS (Ct, rows of BN + 1) to the output
-// table in the write order ubit; returns the largest |re|, |im| written.
-template <int CFG>
+// table in the write order ubit (NT threads); returns the largest |re|, |im|
+// written.
+template <int CFG, int NT = 256>
 __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const float2* Ct,
                                                 int64_t row0, int64_t col0, int64_t key,
                                                 int64_t row_end, int64_t col_end,
@@ -481,17 +490,19 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
                                                 int r_tid, int c_tid) {
   using T = TileInfo<CFG, 0>;
   constexpr int BM = T::BM, BN = T::BN;
+  constexpr int LOG_NT = NT == 512 ? 9 : 8;
+  constexpr int PER_THREAD = BM * BN / NT;
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t sizeC = M * N;
   const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.mapM) : 0;
   const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.mapN) : 0;
   float amax = 0.f;
 #pragma unroll 4
-  for (int t = 0; t < T::PER_THREAD; ++t) {
+  for (int t = 0; t < PER_THREAD; ++t) {
     int r = r_tid, c = c_tid;
 #pragma unroll
-    for (int b = 8; b < T::UBITS; ++b) {
-      if ((t >> (b - 8)) & 1) {
+    for (int b = LOG_NT; b < T::UBITS; ++b) {
+      if ((t >> (b - LOG_NT)) & 1) {
         const int u = g.ubit[b];
         if (u < 32)
           r |= 1 << u;
@@ -1026,6 +1037,194 @@ __global__ void __launch_bounds__(256 * KG) k_contract_split(ContractArgs g) {
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
 
+// Split FP16 / BF16 contraction on 128 x 128 tiles with eight waves and
+// double-buffered LDS (tile 5).  Waves form a 4 x 2 grid; each computes a
+// 32 x 64 block pair (two 32x32x16 MFMA blocks sharing the row fragment)
+// with two accumulators per block, as in k_contract_split.  K runs in slabs
+// of 16 complex; while the waves multiply slab i out of one LDS buffer, the
+// hi/lo planes of slab i + 1 (already in registers) are written to the other
+// buffer and the global loads of slab i + 2 are issued, so one barrier per
+// slab separates the phases and each SIMD holds two waves whose MFMA and
+// staging work interleave.  At the end of a tile the result is parked in LDS
+// (over both buffers) and written in the output's bit order; the first slab
+// of the next tile is already in registers by then.  Thread t stages row
+// t / 4, complex 4 (t % 4) .. 4 (t % 4) + 3 of both operands' slabs.
+template <int PREC>
+__global__ void __launch_bounds__(512) k_contract_split_db(ContractArgs g) {
+  constexpr int BM = 128, BN = 128, TK = 16, KP = TK + 8;  // halves per plane row
+  constexpr int PL_A = BM * KP, PL_B = BN * KP;            // halves per plane
+  constexpr int BUF = 4 * (PL_A + PL_B);                   // halves per buffer
+  constexpr int LDS_MAIN = BUF;                            // floats: two buffers of halves
+  constexpr int LDS_EPI = BM * (BN + 1) * 2;
+  constexpr int LDS_TOTAL = LDS_MAIN > LDS_EPI ? LDS_MAIN : LDS_EPI;
+  typedef float accv __attribute__((ext_vector_type(16)));
+  __shared__ __attribute__((aligned(16))) float smem[LDS_TOTAL];
+  __shared__ int64_t dep_m_lo[BM];
+  __shared__ int64_t dep_n_lo[BN];
+  uint16_t* lds = reinterpret_cast<uint16_t*>(smem);
+  float2* Ct = reinterpret_cast<float2*>(smem);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // rows 32 wm .., columns 64 wn ..
+  const TileMap<BM, BN> tmap(g);
+  const int64_t tiles = tmap.tiles;
+  const int64_t items = tiles * g.ksplit;
+  const int64_t per_xcd = (items + 7) / 8;
+  const int64_t walk = per_xcd * 8;
+  const int64_t K = int64_t(1) << g.kb;
+  const int64_t Kc = K / g.ksplit;
+  const int row_shift = g.kb + 3;  // bytes per operand row = 2^row_shift
+
+  int eA = 0, eB = 0;
+  if constexpr (PREC == 1) {
+    eA = fp16_scale_exp(g.amaxA, g.amax_nA);
+    eB = fp16_scale_exp(g.amaxB, g.amax_nB);
+  }
+  const float sA = ldexpf(1.f, eA), sB = ldexpf(1.f, eB), s_out = ldexpf(1.f, -(eA + eB));
+  float amax = 0.f;
+
+  int r_tid = 0, c_tid = 0;
+  epilogue_setup<5, 512>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
+  __syncthreads();
+
+  auto item_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
+  auto next_p = [&](int64_t p) -> int64_t {
+    for (p += gridDim.x; p < walk; p += gridDim.x)
+      if (item_of(p) < items) return p;
+    return walk;
+  };
+  auto k_begin = [&](int64_t item) -> int64_t { return (item / tiles) * Kc; };
+
+  const int srow = tid >> 2, sq = tid & 3;
+  float4 ra0, ra1, rb0, rb1;
+  // One slab of both operands into registers: zero beyond the K chunk end;
+  // rows past an operand's end re-read its last row (never written out).
+  auto fetch = [&](const TileOrigin& o, int64_t k0, int64_t klim) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t gk = k0 + 4 * sq;
+    if (gk >= klim) {
+      ra0 = ra1 = rb0 = rb1 = z;
+      return;
+    }
+    const int64_t la = o.row_end - o.row0 - 1, lb = o.col_end - o.col0 - 1;
+    const uint32_t rra = uint32_t(srow < la ? srow : la), rrb = uint32_t(srow < lb ? srow : lb);
+    const char* pa = reinterpret_cast<const char*>(g.A + (o.row0 << g.kb) + k0) + ((rra << row_shift) + 32u * sq);
+    const char* pb = reinterpret_cast<const char*>(g.B + (o.col0 << g.kb) + k0) + ((rrb << row_shift) + 32u * sq);
+    const bool two = gk + 2 < klim;
+    ra0 = *reinterpret_cast<const float4*>(pa);
+    rb0 = *reinterpret_cast<const float4*>(pb);
+    ra1 = two ? *reinterpret_cast<const float4*>(pa + 16) : z;
+    rb1 = two ? *reinterpret_cast<const float4*>(pb + 16) : z;
+  };
+  auto stage = [&](uint16_t* buf) {
+    split_store4<PREC>(ra0, ra1, sA, buf + srow * KP + 4 * sq, PL_A);
+    split_store4<PREC>(rb0, rb1, sB, buf + 4 * PL_A + srow * KP + 4 * sq, PL_B);
+  };
+
+  int64_t p = blockIdx.x;
+  if (p < walk && item_of(p) >= items) p = next_p(p);
+  if (p >= walk) {
+    if (g.amax_out) publish_amax(0.f, g.amax_out, g.epoch);
+    return;
+  }
+  TileOrigin cur = tmap.at(g, item_of(p) % tiles);
+  fetch(cur, k_begin(item_of(p)), k_begin(item_of(p)) + Kc);
+
+  const int li = lane & 31, lg = lane >> 5;
+  while (p < walk) {
+    const int64_t item = item_of(p);
+    const TileOrigin o = cur;
+    const int64_t kbeg = k_begin(item), kend = kbeg + Kc;
+    const int nslabs = int((Kc + TK - 1) / TK);
+    const int64_t pn = next_p(p);
+
+    accv acc_re[2], acc_im[2];
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc_re[fn][v] = acc_im[fn][v] = 0.f;
+
+    // Registers hold this tile's slab 0.
+    stage(lds);
+    if (nslabs > 1) {
+      fetch(o, kbeg + TK, kend);
+    } else if (pn < walk) {
+      cur = tmap.at(g, item_of(pn) % tiles);
+      fetch(cur, k_begin(item_of(pn)), k_begin(item_of(pn)) + Kc);
+    }
+    __syncthreads();
+    for (int i = 0; i < nslabs; ++i) {
+      const uint16_t* bc = lds + (i & 1) * BUF;
+      if (i + 1 < nslabs) {
+        stage(lds + ((i & 1) ^ 1) * BUF);
+        if (i + 2 < nslabs) {
+          fetch(o, kbeg + int64_t(i + 2) * TK, kend);
+        } else if (pn < walk) {
+          cur = tmap.at(g, item_of(pn) % tiles);
+          fetch(cur, k_begin(item_of(pn)), k_begin(item_of(pn)) + Kc);
+        }
+      }
+      const uint16_t* a = bc + (wm * 32 + li) * KP + 8 * lg;
+      const u32x4 arh = *reinterpret_cast<const u32x4*>(a);
+      const u32x4 aih = *reinterpret_cast<const u32x4*>(a + PL_A);
+      const u32x4 arl = *reinterpret_cast<const u32x4*>(a + 2 * PL_A);
+      const u32x4 ail = *reinterpret_cast<const u32x4*>(a + 3 * PL_A);
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn) {
+        const uint16_t* b = bc + 4 * PL_A + (wn * 64 + fn * 32 + li) * KP + 8 * lg;
+        const u32x4 brh = *reinterpret_cast<const u32x4*>(b);
+        const u32x4 bih = *reinterpret_cast<const u32x4*>(b + PL_B);
+        const u32x4 brl = *reinterpret_cast<const u32x4*>(b + 2 * PL_B);
+        const u32x4 bil = *reinterpret_cast<const u32x4*>(b + 3 * PL_B);
+        const u32x4 nbih = bih ^ 0x80008000u, nbil = bil ^ 0x80008000u;
+#define XEB_MMA(acc, x, y) acc = mma_split<32, PREC>(x, y, acc)
+        XEB_MMA(acc_re[fn], arh, brh);
+        XEB_MMA(acc_im[fn], arh, bih);
+        XEB_MMA(acc_re[fn], aih, nbih);
+        XEB_MMA(acc_im[fn], aih, brh);
+        XEB_MMA(acc_re[fn], arh, brl);
+        XEB_MMA(acc_im[fn], arh, bil);
+        XEB_MMA(acc_re[fn], aih, nbil);
+        XEB_MMA(acc_im[fn], aih, brl);
+        XEB_MMA(acc_re[fn], arl, brh);
+        XEB_MMA(acc_im[fn], arl, bih);
+        XEB_MMA(acc_re[fn], ail, nbih);
+        XEB_MMA(acc_im[fn], ail, brh);
+#undef XEB_MMA
+      }
+      __syncthreads();
+    }
+
+    // 32x32 results: lane l, register v hold row (v % 4) + 4 (l / 32) +
+    // 8 (v / 4), column l % 32 of the block.
+    auto for_each_result = [&](auto&& f) {
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int r = wm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+          const int c = wn * 64 + fn * 32 + (lane & 31);
+          f(r, c, make_float2(acc_re[fn][v] * s_out, acc_im[fn][v] * s_out));
+        }
+    };
+    if (g.ksplit > 1) {
+      float2* dst = g.partial + item * (BM * BN);
+      for_each_result([&](int r, int c, float2 x) { dst[r * BN + c] = x; });
+      p = pn;
+      continue;
+    }
+    for_each_result([&](int r, int c, float2 x) { Ct[r * (BN + 1) + c] = x; });
+    __syncthreads();
+    amax = fmaxf(amax, epilogue_write<5, 512>(g, Ct, o.row0, o.col0, o.key, o.row_end, o.col_end,
+                                              dep_m_lo, dep_n_lo, r_tid, c_tid));
+    __syncthreads();
+    p = pn;
+  }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+}
+
 // Split-K chunk sum: partial[0] += partial[1] + ... + partial[ksplit - 1],
 // element by element in chunk order (deterministic), two complex per thread.
 __global__ void __launch_bounds__(256) k_splitk_sum(float4* partial, int64_t chunk_f4, int ksplit) {
@@ -1185,6 +1384,8 @@ unsigned persistent_grid(int64_t tiles) {
     hipError_t e;
     if constexpr (PREC == 0)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV, KG>, 256 * KG, 0);
+    else if constexpr (CFG == 5)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split_db<PREC>, 512, 0);
     else
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split<CFG, PREC, TKV, KG>, 256 * KG, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
@@ -1213,6 +1414,9 @@ void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t row
   if constexpr (PREC == 0)
     launch(k_contract_mfma<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
            dim3(256 * KG), s, true, true, a);
+  else if constexpr (CFG == 5)
+    launch(k_contract_split_db<PREC>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)), dim3(512),
+           s, true, true, a);
   else
     launch(k_contract_split<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
            dim3(256 * KG), s, true, true, a);
@@ -1252,6 +1456,8 @@ void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t ro
     launch_cfg<1, PREC, lo>(a, s, rowsA, rowsB);
   } else if (a.tile == 4) {
     launch_cfg<4, PREC, lo>(a, s, rowsA, rowsB);
+  } else if (a.tile == 5) {
+    if constexpr (PREC != 0) launch_cfg<5, PREC, 16>(a, s, rowsA, rowsB);
   } else {
     if (a.tile == 3)
       launch_cfg<3, PREC, lo>(a, s, rowsA, rowsB);
@@ -1298,11 +1504,14 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
     launch_reduce_cfg<2>(a, s, rowsA, rowsB);
   else if (a.tile == 3)
     launch_reduce_cfg<3>(a, s, rowsA, rowsB);
-  else
+  else if (a.tile == 4)
     launch_reduce_cfg<4>(a, s, rowsA, rowsB);
+  else
+    launch_reduce_cfg<5>(a, s, rowsA, rowsB);
 }
 
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
+  if (tile == 5) return prec != 0 && tk == 16 && kg == 1;
   if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
   if (tk == lo) return tile >= 0 && tile <= 4;
@@ -1323,17 +1532,20 @@ void prepare_mfma_launch(int prec) {
     (void)persistent_grid<0, 1, 32, 1>(1), (void)persistent_grid<1, 1, 32, 1>(1);
     (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
     (void)persistent_grid<3, 1, 32, 1>(1), (void)persistent_grid<4, 1, 32, 1>(1);
+    (void)persistent_grid<5, 1, 16, 1>(1);
     (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
     (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
     (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
     (void)persistent_grid<3, 2, 32, 1>(1), (void)persistent_grid<4, 2, 32, 1>(1);
+    (void)persistent_grid<5, 2, 16, 1>(1);
     (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128}, kBN[kMfmaTiles] = {64, 128, 256, 16, 128};
+  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128, 128};
+  static const int kBN[kMfmaTiles] = {64, 128, 256, 16, 128, 128};
   const int t = tile >= 0 && tile < kMfmaTiles ? tile : 0;
   *bm = kBM[t];
   *bn = kBN[t];

@@ -444,18 +444,20 @@ def test_every_mfma_variant_vs_state_vector(precision):
                 assert used > 0
 
 
-@pytest.mark.parametrize("precision", ["c64", "split_fp16", "split_bf16"])
-def test_wide_tile_vs_state_vector(precision):
-    """The 128x128 tile (four 32x32 blocks per wave) forced on every
-    MFMA-capable node, unsplit, with split K, and in the keyed form where a
-    key's product spans at least 64 x 64: amplitudes within the bound of the
-    state vector, reruns bit-identical."""
+@pytest.mark.parametrize("precision,tile", [("c64", 4), ("split_fp16", 4), ("split_bf16", 4),
+                                            ("split_fp16", 5), ("split_bf16", 5)])
+def test_wide_tile_vs_state_vector(precision, tile):
+    """The 128x128 tiles (4: four 32x32 blocks per wave; 5: eight waves with
+    double-buffered LDS, split forms) forced on every MFMA-capable node,
+    unsplit, with split K, and in the keyed form where a key's product spans
+    at least 64 x 64: amplitudes within the bound of the state vector, reruns
+    bit-identical."""
     tol = AMP_TOL if precision == "c64" else SPLIT_TOL
     circ = grid_circuit(4, 5, 14, seed=14 * 7 + 4000)
     strings = prefix_bitstrings(20, 4000, 12, 5)
     ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
     ref = statevec.state_vector(circ)[strings.astype(np.int64)]
-    lo = 16 if precision == "c64" else 32
+    lo = 16 if precision == "c64" or tile == 5 else 32
     p = xeb.Plan(circ, strings, ch, sl, precision=precision, stack_slices=1, **SMALL_MFMA)
     nodes = [ns for ns in p.all_node_stats() if ns["kernel"] == "mfma"]
     assert nodes
@@ -470,7 +472,7 @@ def test_wide_tile_vs_state_vector(precision):
                 rb, cb = (ns["n_bits"], ns["m_bits"]) if ns["swapped"] else (ns["m_bits"], ns["n_bits"])
                 keyed = 1 if rb >= 6 and cb >= 6 else 0
             try:
-                p.set_node_config(ns["node"], "mfma", tile=4, swapped=ns["swapped"], ksplit=ks,
+                p.set_node_config(ns["node"], "mfma", tile=tile, swapped=ns["swapped"], ksplit=ks,
                                   k_slab=lo, k_groups=1, keyed=keyed)
             except xeb.XebError:
                 continue
