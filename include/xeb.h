@@ -123,6 +123,12 @@ typedef struct {
                              bits grow by 2^(their count); launches fall by up to 2^J,
                              and a node whose low slice bits are sparse is no longer
                              recomputed for slices that do not change its key. */
+  uint64_t open_qubits;   /* multi-batch output (section "Multi-batch simulator"): the
+                             output legs of these qubits (bit q = qubit q, at most 16
+                             of them, w = their count) stay open, so each string yields
+                             the 2^w amplitudes of the strings that agree with it on
+                             every other qubit; the strings' open bits select nothing
+                             and only the XEB reads them.  Default 0. */
 } xeb_options_t;
 
 typedef struct {
@@ -142,6 +148,7 @@ typedef struct {
   uint64_t workspace_bytes;
   int64_t n_blocks;          /* string blocks chosen by the dry run (1 = all strings at once) */
   int32_t n_stacked;         /* J of xeb_options_t.stack_slices */
+  int32_t n_open;            /* w: open output qubits; amps hold k * 2^w values */
 } xeb_stats_t;
 
 #define XEB_KERNEL_GENERIC 0  /* per-element kernel (small or sparse nodes) */
@@ -250,6 +257,9 @@ int xeb_plan_bind_workspace(xeb_plan_t plan, void* dev_ptr, uint64_t bytes);
  * each string's sum over those slices into amps.
  *   amps (device) complex128 [k] ((re, im) doubles), in the order of the
  *     bitstrings passed to xeb_plan_create; zero it before the first call.
+ *     With w open qubits it is complex128 [k][2^w]: entry (i, o) is the
+ *     amplitude of string i with its open qubits set to o (bit j of o = the
+ *     j-th open qubit in increasing order).
  *     Each call adds its slices' partial amplitudes (FP32 complex results of
  *     the contraction, widened to FP64) in increasing slice order with
  *     Neumaier compensation and folds the compensation into amps at the end
@@ -269,8 +279,9 @@ int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* 
 /*
  * Linear XEB, Eq. (1): F = (2^n / k) sum_i |amps[i]|^2 - 1 over all k strings
  * (duplicates with multiplicity), summed in FP64 with compensation on the
- * device in a fixed order.  amps (device) complex128 [k].  Waits for the stream
- * and writes *F (host).
+ * device in a fixed order.  amps (device) complex128 [k] (with open qubits
+ * [k][2^w], of which each string's own entry, its open bits as o, counts).
+ * Waits for the stream and writes *F (host).
  * Errors: XEB_EINVAL (k == 0 or NULL F), XEB_ESTATE (no workspace), XEB_EHIP.
  */
 int xeb_fidelity(xeb_plan_t plan, const void* amps, void* stream, double* F);

@@ -101,11 +101,9 @@ Batch* create_batch(Plan* const* plans, void* const* amps, int n) {
       if (p->k == 0) continue;
       hipStream_t st = side[i % nside];
       p->capturing = true;
-      launch_zero(b->amps[i], uint64_t(p->k) * 16, st);
+      launch_zero(b->amps[i], (uint64_t(p->k) << p->w) * 16, st);
       contract_plan(p, 0, int64_t(1) << p->s, b->amps[i], st);
-      double* out = reinterpret_cast<double*>(static_cast<char*>(p->ws) + p->off_scratch);
-      launch_xeb(static_cast<const double2*>(b->amps[i]), p->k, p->n_qubits, out, st);
-      hip_check(hipGetLastError(), "xeb launch");
+      launch_plan_xeb(p, b->amps[i], st);
       p->capturing = false;
     }
     for (int j = 0; j < nside; ++j) {

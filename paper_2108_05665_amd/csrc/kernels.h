@@ -103,14 +103,18 @@ int64_t mfma_tiles(int tile, int64_t rowsA, int64_t rowsB);
 void prepare_mfma_launch(int prec);
 
 // Cross-slice accumulation (Appendix A, "Slicing": sum over assignments) in
-// FP64 with Neumaier compensation.  Group g < n adds, into amps[idx[g]], the
-// root partials partial[rho[j]] of its entries j = eoff[g] .. eoff[g + 1] - 1
-// in entry order (increasing low slice key), each only if its slice
-// base + slo[j] lies in [lo, hi).
+// FP64 with Neumaier compensation.  Every root key holds W = 2^w values (w
+// open qubits, else W = 1).  Group g < n adds, into amps[idx[g] W + o] for
+// o < W, the root partials partial[rho[j] W + o] of its entries
+// j = eoff[g] .. eoff[g + 1] - 1 in entry order (increasing low slice key),
+// each only if its slice base + slo[j] lies in [lo, hi).
 void launch_zero(void* p, uint64_t bytes, hipStream_t s);
 void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* eoff,
                        const int32_t* rho, const int32_t* slo, int64_t base, int64_t lo,
-                       int64_t hi, double2* amps, double2* comp, int64_t n, hipStream_t s);
+                       int64_t hi, double2* amps, double2* comp, int64_t n, int w, hipStream_t s);
+// own[i] = amps[i 2^w + sel[i]], i < k (each string's own amplitude).
+void launch_gather_own(const double2* amps, const int32_t* sel, int w, double2* own, int64_t k,
+                       hipStream_t s);
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s);
 
 // Linear XEB (Eq. 1): F = 2^n / k * sum |amps|^2 - 1, a compensated FP64

@@ -1281,22 +1281,31 @@ __global__ void k_zero(uint32_t* p, uint64_t words) {
     p[i] = 0u;
 }
 
+// Thread t adds value o = t mod 2^w of group g = t / 2^w.
 __global__ void k_accumulate(const float2* partial, const int32_t* idx, const int32_t* eoff,
                              const int32_t* rho, const int32_t* slo, int64_t base, int64_t lo,
-                             int64_t hi, double2* amps, double2* comp, int64_t n) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                             int64_t hi, double2* amps, double2* comp, int64_t n, int w) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t g = t >> w;
   if (g >= n) return;
-  const int64_t i = idx[g];
+  const int64_t o = t & ((int64_t(1) << w) - 1);
+  const int64_t i = (int64_t(idx[g]) << w) + o;
   double2 s = amps[i], c = comp[i];
   for (int32_t j = eoff[g], end = eoff[g + 1]; j < end; ++j) {
     const int64_t sigma = base + slo[j];
     if (sigma < lo || sigma >= hi) continue;
-    const float2 p = partial[rho[j]];
+    const float2 p = partial[(int64_t(rho[j]) << w) + o];
     neumaier(s.x, c.x, double(p.x));
     neumaier(s.y, c.y, double(p.y));
   }
   amps[i] = s;
   comp[i] = c;
+}
+
+__global__ void k_gather_own(const double2* amps, const int32_t* sel, int w, double2* own, int64_t k) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  own[i] = amps[(i << w) + sel[i]];
 }
 
 __global__ void k_fold(double2* amps, const double2* comp, int64_t k) {
@@ -1565,10 +1574,16 @@ void launch_zero(void* p, uint64_t bytes, hipStream_t s) {
 
 void launch_accumulate(const float2* partial, const int32_t* idx, const int32_t* eoff,
                        const int32_t* rho, const int32_t* slo, int64_t base, int64_t lo,
-                       int64_t hi, double2* amps, double2* comp, int64_t n, hipStream_t s) {
+                       int64_t hi, double2* amps, double2* comp, int64_t n, int w, hipStream_t s) {
   if (n <= 0) return;
-  launch(k_accumulate, dim3(grid_for(n, 256)), dim3(256), s, true, true, partial, idx, eoff, rho,
-         slo, base, lo, hi, amps, comp, n);
+  launch(k_accumulate, dim3(grid_for(n << w, 256)), dim3(256), s, true, true, partial, idx, eoff,
+         rho, slo, base, lo, hi, amps, comp, n, w);
+}
+
+void launch_gather_own(const double2* amps, const int32_t* sel, int w, double2* own, int64_t k,
+                       hipStream_t s) {
+  if (k <= 0) return;
+  k_gather_own<<<grid_for(k, 256), 256, 0, s>>>(amps, sel, w, own, k);
 }
 
 void launch_fold_compensation(double2* amps, const double2* comp, int64_t k, hipStream_t s) {

@@ -260,6 +260,13 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   const int n = net.n_qubits;
   p.n_qubits = n;
 
+  // ---- open output qubits (multi-batch output) ------------------------------
+  const uint64_t open = o.open_qubits;
+  if (n < 64 && (open >> n) != 0) fail(XEB_EINVAL, "open_qubits names a qubit at or above n_qubits");
+  const int w = popcount64(open);
+  if (w > 16) fail(XEB_EINVAL, "at most 16 open qubits");
+  p.w = w;
+
   // ---- strings ----------------------------------------------------------
   if (k < 0) fail(XEB_EINVAL, "k is negative");
   if (k > (int64_t(1) << 31) - 1) fail(XEB_EINVAL, "k exceeds 2^31 - 1");
@@ -316,7 +323,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     Node& nd = p.nodes[j];
     for (int32_t leg : net.leaves[j].legs) {
       const int q = net.leg_qubit[leg];
-      if (q >= 0)
+      if (q >= 0 && ((open >> q) & 1))
+        nd.legs.push_back(leg);  // open output leg: a tensor leg up to the root
+      else if (q >= 0)
         nd.outmask |= uint64_t(1) << q;
       else if (slot[leg] >= 0 && slot[leg] < J)
         nd.outmask |= uint64_t(1) << (n + slot[leg]);  // stacked: a key bit
@@ -338,7 +347,16 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     nd.smask = a.smask | b.smask;
     if (nd.legs.size() > size_t(kMaxBits)) fail(XEB_EINVAL, "intermediate tensor has too many legs");
   }
-  if (!p.nodes[p.root].legs.empty()) fail(XEB_EINVAL, "the tree does not close the network");
+  // The root keeps exactly the open output legs, ordered by qubit (bit j of a
+  // root element's index = the j-th open qubit).
+  {
+    std::vector<int32_t>& rl = p.nodes[p.root].legs;
+    for (int32_t leg : rl)
+      if (net.leg_qubit[leg] < 0) fail(XEB_EINVAL, "the tree does not close the network");
+    if (int(rl.size()) != w) fail(XEB_EINVAL, "internal: open legs missing at the root");
+    std::sort(rl.begin(), rl.end(),
+              [&](int32_t x, int32_t y) { return net.leg_qubit[x] < net.leg_qubit[y]; });
+  }
 
   // ---- layouts (top-down) -------------------------------------------------
   std::vector<int> pos(net.n_legs, -1);
@@ -386,7 +404,9 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   // in depth-first leaf order; a stacked slice bit sits on the two leaves its
   // leg joins, and only its first occurrence enters the sort key, so the
   // concatenated key has n + J <= 64 bits.
-  std::vector<uint64_t> dr(bits, bits + k);
+  // (Open bits are no key: strings that differ only there share one entry.)
+  std::vector<uint64_t> dr(k);
+  for (int64_t i = 0; i < k; ++i) dr[i] = bits[i] & ~open;
   std::sort(dr.begin(), dr.end());
   dr.erase(std::unique(dr.begin(), dr.end()), dr.end());
   const int64_t kdr = int64_t(dr.size());
@@ -451,7 +471,8 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   }
   // Distinct string of every input string.
   std::vector<int64_t> where(k);
-  for (int64_t i = 0; i < k; ++i) where[i] = std::lower_bound(dr.begin(), dr.end(), bits[i]) - dr.begin();
+  for (int64_t i = 0; i < k; ++i)
+    where[i] = std::lower_bound(dr.begin(), dr.end(), bits[i] & ~open) - dr.begin();
 
   // Keys of every internal node among the strings [first, first + count).
   auto build_block = [&](int64_t first, int64_t count) {
@@ -560,6 +581,10 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     }
     p.off_leaf_amax = off;
     off += align_up(uint64_t(nn) * 8);
+    if (w > 0) {
+      p.off_sel = off;
+      off += align_up(uint64_t(k) * 4);
+    }
     const uint64_t static_end = off;
     // Node tables.  A table is transient when its parent is only ever
     // evaluated right after it within the same slice step: then it lives from
@@ -654,7 +679,11 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     p.partial_bytes = align_up(partial);
     off += p.partial_bytes;
     p.off_comp = off;
-    off += align_up(uint64_t(k) * 16);
+    off += align_up((uint64_t(k) << w) * 16);
+    if (w > 0) {
+      p.off_gather = off;
+      off += align_up(uint64_t(k) * 16);
+    }
     p.off_scratch = off;
     off += align_up(xeb_scratch_bytes(k));
     p.ws_bytes = off;
@@ -751,6 +780,11 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     put(blk.off_rho, blk.rho);
     put(blk.off_slo, blk.slo);
   }
+  if (w > 0) {
+    std::vector<int32_t> sel(k);
+    for (int64_t i = 0; i < k; ++i) sel[i] = int32_t(pext64(bits[i], open));
+    put(p.off_sel, sel);
+  }
 
   // ---- stats -----------------------------------------------------------------
   xeb_stats_t& st = p.stats;
@@ -762,6 +796,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   st.n_qubits = n;
   st.n_sliced = s;
   st.n_stacked = J;
+  st.n_open = w;
   st.n_blocks = int64_t(p.blocks.size());
   for (int T = 0; T < nn; ++T)
     st.max_tensor_elems = std::max<int64_t>(st.max_tensor_elems, p.nodes[T].size());
@@ -995,7 +1030,7 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
   DeviceGuard g(p->opt.device);
   char* ws = static_cast<char*>(p->ws);
   double2* comp = reinterpret_cast<double2*>(ws + p->off_comp);
-  launch_zero(comp, uint64_t(p->k) * 16, stream);
+  launch_zero(comp, (uint64_t(p->k) << p->w) * 16, stream);
   // Every call starts from its first slice: no table computed by an earlier
   // call is reused, so a call's cost does not depend on its predecessors.
   for (Node& nd : p->nodes) {
@@ -1056,13 +1091,26 @@ void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream
                           reinterpret_cast<const int32_t*>(ws + blk.off_eoff),
                           reinterpret_cast<const int32_t*>(ws + blk.off_rho),
                           reinterpret_cast<const int32_t*>(ws + blk.off_slo), sigma << J, b, e,
-                          static_cast<double2*>(amps), comp, ng, stream);
+                          static_cast<double2*>(amps), comp, ng, p->w, stream);
       });
       hip_check(hipGetLastError(), "accumulate launch");
     }
   }
-  launch_fold_compensation(static_cast<double2*>(amps), comp, p->k, stream);
+  launch_fold_compensation(static_cast<double2*>(amps), comp, p->k << p->w, stream);
   hip_check(hipGetLastError(), "fold launch");
+}
+
+void launch_plan_xeb(Plan* p, const void* amps, hipStream_t stream) {
+  char* ws = static_cast<char*>(p->ws);
+  const double2* a = static_cast<const double2*>(amps);
+  if (p->w > 0) {
+    // Each string's own amplitude: entry (i, open bits of string i).
+    double2* own = reinterpret_cast<double2*>(ws + p->off_gather);
+    launch_gather_own(a, reinterpret_cast<const int32_t*>(ws + p->off_sel), p->w, own, p->k, stream);
+    a = own;
+  }
+  launch_xeb(a, p->k, p->n_qubits, ws + p->off_scratch, stream);
+  hip_check(hipGetLastError(), "xeb launch");
 }
 
 double fidelity_plan(Plan* p, const void* amps, hipStream_t stream) {
@@ -1071,8 +1119,7 @@ double fidelity_plan(Plan* p, const void* amps, hipStream_t stream) {
   if (!amps) fail(XEB_EINVAL, "amps is NULL");
   DeviceGuard g(p->opt.device);
   double* out = reinterpret_cast<double*>(static_cast<char*>(p->ws) + p->off_scratch);
-  launch_xeb(static_cast<const double2*>(amps), p->k, p->n_qubits, out, stream);
-  hip_check(hipGetLastError(), "xeb launch");
+  launch_plan_xeb(p, amps, stream);
   double F = 0.0;
   hip_check(hipMemcpyAsync(&F, out, sizeof(double), hipMemcpyDeviceToHost, stream), "xeb copy");
   hip_check(hipStreamSynchronize(stream), "xeb sync");

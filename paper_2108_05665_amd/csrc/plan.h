@@ -93,6 +93,9 @@ struct Plan {
   int n_qubits = 0;
   int s = 0;
   int sj = 0;  // stacked low slice bits (xeb_options_t::stack_slices)
+  int w = 0;   // open output qubits (xeb_options_t::open_qubits): 2^w values per string
+  uint64_t off_sel = 0;     // static: open bits of each string (int32 [k]), when w > 0
+  uint64_t off_gather = 0;  // dynamic: each string's own amplitude (complex128 [k]), w > 0
   std::vector<int32_t> sliced;
   int64_t k = 0, kd = 0;
   int n_leaves = 0;
@@ -122,6 +125,8 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bitstrings, i
 void bind_plan(Plan* p, void* dev, uint64_t bytes);
 void contract_plan(Plan* p, int64_t b, int64_t e, void* amps, hipStream_t stream);
 double fidelity_plan(Plan* p, const void* amps, hipStream_t stream);
+// Enqueues the XEB of the plan's amplitudes; F lands in the workspace scratch.
+void launch_plan_xeb(Plan* p, const void* amps, hipStream_t stream);
 
 void hip_check(hipError_t e, const char* what);
 

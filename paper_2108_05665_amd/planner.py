@@ -30,12 +30,17 @@ from . import xeb as _xeb
 
 
 class Structure:
-    """Leaf legs (internal legs only) and output masks of a circuit's network."""
+    """Leaf legs (internal legs only) and output masks of a circuit's network.
 
-    def __init__(self, circ, fuse_1q=True, fold_kets=True):
+    The output legs of `open_qubits` (multi-batch output) stay tensor legs up
+    to the root and are in `open_legs`; they are never sliced."""
+
+    def __init__(self, circ, fuse_1q=True, fold_kets=True, open_qubits: int = 0):
         leaves, n_legs, leg_qubit = _xeb.network_describe(circ, fuse_1q, fold_kets)
         self.n_legs = n_legs
         self.leg_qubit = leg_qubit
+        self.open_legs = frozenset(l for l, q in enumerate(leg_qubit)
+                                   if q >= 0 and (open_qubits >> q) & 1)
         self.legs = []
         self.outmask = []
         for legs in leaves:
@@ -43,7 +48,7 @@ class Structure:
             internal = []
             for l in legs:
                 q = leg_qubit[l]
-                if q >= 0:
+                if q >= 0 and l not in self.open_legs:
                     om |= 1 << q
                 else:
                     internal.append(l)
@@ -204,6 +209,7 @@ def greedy_slices(st: Structure, children, count: VariantCounter, n_slice: int):
         if not cand:
             for x in legs:
                 cand |= x
+        cand -= st.open_legs
         best = None
         for l in sorted(cand):
             _, mx, _, sec = tree_cost(st, children, count, sliced | {l})
@@ -274,7 +280,9 @@ def _run_anneals(st, count, jobs, workers):
 def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
          temp: float = 0.3, fuse_1q: bool = True, fold_kets: bool = True,
          objective: str = "time", anneal_steps: int = 0, anneal_restarts: int = 4,
-         size_log2_max=None, table_bytes_max=None, workers: int = 1):
+         size_log2_max=None, table_bytes_max=None, workers: int = 1, open_qubits: int = 0,
+         anneal_objective: str = "time", alpha: float = 19.7, memory: str = "tables",
+         slicing: str = "swap", slice_every: int = 20000, beta: float = 8.0):
     """Returns (children [(a, b), ...], sliced_legs [leg of bit 0, ...], info).
 
     Every greedy trial tree is sliced and its slice bits ordered; the kept
@@ -285,9 +293,12 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
     tree's size (or `size_log2_max`), and the best result by estimated time
     under the executor's slice order is returned.  `workers` > 1 runs the
     restarts in that many forked processes (same results as one process; fork
-    before the process touches the GPU)."""
-    st = Structure(circ, fuse_1q, fold_kets)
-    count = VariantCounter(bitstrings)
+    before the process touches the GPU).  anneal_objective, alpha, memory,
+    slicing, slice_every and beta select the optimizer's objective and
+    slicing moves (optimizer.anneal); with slicing "paper" the number of
+    sliced legs floats and n_sliced only seeds the start."""
+    st = Structure(circ, fuse_1q, fold_kets, open_qubits)
+    count = VariantCounter(np.asarray(bitstrings, dtype=np.uint64) & ~np.uint64(open_qubits))
     if st.n_leaves == 1:
         return [], [], dict(cost=0.0, max_log2=0, seconds=0.0)
     rng = random.Random(seed)
@@ -306,7 +317,9 @@ def plan(circ, bitstrings, n_sliced: int = 0, trials: int = 16, seed: int = 0,
         ch0, sl0, info0 = best[1], best[2], best[3]
         cap = info0["max_log2"] if size_log2_max is None else size_log2_max
         jobs = [dict(children=ch0, sliced=sl0, steps=anneal_steps, size_log2_max=cap,
-                     seed=seed * 1000 + r + 1, mem_max=table_bytes_max)
+                     seed=seed * 1000 + r + 1, mem_max=table_bytes_max, objective=anneal_objective,
+                     alpha=alpha, memory=memory, slicing=slicing, slice_every=slice_every,
+                     beta=beta)
                 for r in range(max(anneal_restarts, 1))]
         for r, (ch, sl, ainfo) in enumerate(_run_anneals(st, count, jobs, workers)):
             order = order_slices(st, ch, count, sl) if sl else []

@@ -71,6 +71,7 @@ class Options(ctypes.Structure):
         ("max_ksplit", ctypes.c_int32),
         ("mfma_min_cmacs", ctypes.c_double),
         ("stack_slices", ctypes.c_int32),
+        ("open_qubits", ctypes.c_uint64),
     ]
 
 
@@ -91,6 +92,7 @@ class Stats(ctypes.Structure):
         ("workspace_bytes", ctypes.c_uint64),
         ("n_blocks", ctypes.c_int64),
         ("n_stacked", ctypes.c_int32),
+        ("n_open", ctypes.c_int32),
     ]
 
 
@@ -252,7 +254,7 @@ class Plan:
     def __init__(self, circ, bitstrings, tree_children, sliced_legs=(), *, fuse_1q=True,
                  fold_kets=True, precision="c64", device=None, memory_budget=0, trace=0,
                  force_generic=False, max_ksplit=0, mfma_min_cmacs=0.0, stack_slices=0,
-                 bind=True):
+                 open_qubits=0, bind=True):
         self._h = _P()
         c, keep = _circuit_struct(circ)
         bs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
@@ -272,11 +274,13 @@ class Plan:
         o.max_ksplit = int(max_ksplit)
         o.mfma_min_cmacs = float(mfma_min_cmacs)
         o.stack_slices = int(stack_slices)
+        o.open_qubits = int(open_qubits)
         _check(_lib.xeb_plan_create(ctypes.byref(c), bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                     bs.size, ctypes.byref(tree),
                                     sl.ctypes.data_as(_I32P) if sl.size else None, sl.size,
                                     ctypes.byref(o), ctypes.byref(self._h)))
         self.k = int(bs.size)
+        self.n_open = bin(int(open_qubits)).count("1")
         self.n_qubits = int(circ.n_qubits)
         self.n_slices = 1 << int(sl.size)
         self.workspace = None
@@ -306,7 +310,8 @@ class Plan:
     def new_amps(self):
         import torch
 
-        return torch.zeros(self.k, dtype=torch.complex128,
+        shape = (self.k,) if self.n_open == 0 else (self.k, 1 << self.n_open)
+        return torch.zeros(shape, dtype=torch.complex128,
                            device=torch.device("cuda", self._device_index))
 
     @staticmethod

@@ -424,3 +424,34 @@ def test_choose_slicing_emulation_mode(budget):
             ch, sl, _ = planner.plan(c, s, n_sliced=ns - 1, trials=3)
             xeb.Plan(c, s, ch, sl, memory_budget=budget, bind=False)
         assert e.value.code == xeb.XEB_ENOMEM
+
+
+@pytest.mark.parametrize("open_q", [0b1, 0b1000000001, 0b111000])
+def test_open_qubits_counts_and_root(open_q):
+    """Multi-batch output (open output legs): the open qubits are no key, so a
+    node's keys are the oracle's brute-force counts over the strings with
+    those bits cleared; the root keeps 2^w elements per key; an open leg is
+    never sliced; a qubit beyond n is refused."""
+    c = grid_circuit(3, 4, 7, 97)
+    s = uniform_bitstrings(12, 200, 98)
+    w = bin(open_q).count("1")
+    ch, sl, _ = planner.plan(c, s, n_sliced=3, trials=3, open_qubits=open_q)
+    net = build_network(c)
+    open_legs = {l for l, q in enumerate(net.leg_qubit) if q >= 0 and (open_q >> q) & 1}
+    assert not open_legs & set(sl)
+    for J in (0, 2):
+        p = xeb.Plan(c, s, ch, sl, open_qubits=open_q, stack_slices=J, bind=False)
+        st = p.stats()
+        assert st["n_open"] == w
+        want = memo.distinct_key_counts(net, memo.Tree(len(net.leaves), ch),
+                                        s & ~np.uint64(open_q))
+        tree = memo.Tree(len(net.leaves), ch)
+        for ns in p.all_node_stats():
+            legs = {l for j in tree.leaves_dfs(ns["node"]) for l in net.leaves[j].legs}
+            low = sum(1 for j, leg in enumerate(sl[:J]) if leg in legs)
+            assert ns["variants"] == want[ns["node"]] << low
+        root = p.node_stats(st["n_leaves"] + st["n_internal"] - 1)
+        # The root's free legs are the open legs: m_bits + n_bits = w.
+        assert root["m_bits"] + root["n_bits"] == w
+    with pytest.raises(xeb.XebError):
+        xeb.Plan(c, s, ch, sl, open_qubits=1 << 12, bind=False)
