@@ -209,8 +209,11 @@ def main() -> int:
                          "(xeb_options_t.stack_slices; 0 = one slice at a time)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager form only (value then comes from it)")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch32"],
-                    help="the 36-qubit workload (default) or the 32-circuit batch")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch32", "share53"],
+                    help="the 36-qubit workload (default), the 32-circuit batch, or one GPU's "
+                         "share of the 53-qubit contraction (a block of slices)")
+    ap.add_argument("--slice-block", type=int, default=256,
+                    help="share53: slices contracted (a contiguous block from slice 0)")
     ap.add_argument("--batch-budget-gib", type=float, default=6.0,
                     help="batch32: HBM workspace budget per circuit")
     ap.add_argument("--batch-max-seconds", type=float, default=2.0,
@@ -221,7 +224,8 @@ def main() -> int:
                          "whose HBM counters calibrate the contraction's")
     args = ap.parse_args()
     if args.precisions is None:
-        args.precisions = "split_fp16,c64" if args.workload == "batch32" else "split_fp16,split_bf16,c64"
+        args.precisions = {"batch32": "split_fp16,c64", "share53": "split_fp16"}.get(
+            args.workload, "split_fp16,split_bf16,c64")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(slices would shard across GPUs with one all-reduce of the amplitudes)",
@@ -230,6 +234,8 @@ def main() -> int:
 
     if args.workload == "batch32":
         return batch_main(args)
+    if args.workload == "share53":
+        return share53_main(args)
 
     import numpy as np
     import torch
@@ -637,6 +643,103 @@ def batch_main(args) -> int:
                          "graphs": r["graphs"], "plans_run_eagerly": r["eager"],
                          "xeb": r["F"]}
                   for prec, r in results.items()},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+SHARE53 = "share_53q_m14"
+SHARE53_PLAN = os.path.join(ROOT, "tests", "data", f"{SHARE53}_plan.json")
+SHARE53_GOLDEN = os.path.join(ROOT, "tests", "golden", f"{SHARE53}_partials.json")
+SHARE53_BUDGET = 270 * 2**30
+
+
+def share53_main(args) -> int:
+    """One GPU's share of the 53-qubit contraction (6x9 grid minus site
+    (0, 4), 14 cycles, 3 * 10^5 uniform strings): the plan fixture's tree and
+    sliced legs, compiled within 270 GiB of HBM; a contiguous block of slices
+    [0, --slice-block) contracted with the memo tables in split FP16 (and
+    the other --precisions).  Reports the time per slice and the full
+    contraction extrapolated as t_block * 2^s / block, and checks single-slice
+    partials of the first strings against the stored FP64 oracle values
+    (no amplitude or XEB: a partial block yields neither)."""
+    import numpy as np
+
+    from synth import config_circuit, config_bitstrings
+    from paper_2108_05665_amd import planner, xeb
+
+    circ = config_circuit(SHARE53)
+    strings = config_bitstrings(SHARE53, circ.n_qubits)
+    if args.plan_only:
+        t0 = time.perf_counter()
+        ch, sl, info = planner.plan(circ, strings, n_sliced=20, trials=8, seed=0, anneal_steps=200000,
+                                    anneal_restarts=4, workers=4, anneal_objective="paper",
+                                    table_bytes_max=250 * 2**30, memory="tables", slicing="paper",
+                                    slice_every=5000, size_log2_max=34)
+        with open(args.plan_only, "w") as f:
+            json.dump({"workload": SHARE53, "children": [[int(a), int(b)] for a, b in ch],
+                       "sliced": [int(x) for x in sl], "info": info}, f)
+        log(f"planned in {time.perf_counter() - t0:.0f} s: cost {info['cost']:.3e}, s = {len(sl)}")
+        return 0
+    import torch
+
+    with open(SHARE53_PLAN) as f:
+        fx = json.load(f)
+    precs = [p.strip() for p in (args.precisions or "split_fp16").split(",") if p.strip()]
+    n_slices = 1 << len(fx["sliced"])
+    block = min(args.slice_block, n_slices)
+    gold = None
+    if os.path.exists(SHARE53_GOLDEN):
+        with open(SHARE53_GOLDEN) as f:
+            gold = json.load(f)
+    results = {}
+    for prec in precs:
+        t0 = time.perf_counter()
+        plan = xeb.Plan(circ, strings, fx["children"], fx["sliced"], precision=prec,
+                        memory_budget=SHARE53_BUDGET)
+        st = plan.stats()
+        t_plan = time.perf_counter() - t0
+        log(f"{prec}: plan compiled and bound in {t_plan:.1f} s, workspace "
+            f"{st['workspace_bytes'] / 2**30:.1f} GiB, {st['n_blocks']} string blocks")
+        parity = None
+        if gold is not None:
+            errs = []
+            for sigma in gold["sigmas"]:
+                a = plan.new_amps()
+                plan.contract(a, sigma, sigma + 1)
+                torch.cuda.synchronize()
+                got = a[: gold["n_strings"]].cpu().numpy()
+                ref = np.array([complex(*x["partial"]) for x in gold["partials"] if x["sigma"] == sigma])
+                errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+                log(f"{prec}: slice {sigma} partials vs oracle {errs[-1]:.2e}")
+            parity = {"sigmas": gold["sigmas"], "strings": gold["n_strings"], "rel_err": errs}
+        amps = plan.new_amps()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(0, block, 16):
+            plan.contract(amps, b, min(b + 16, block))
+            torch.cuda.synchronize()
+            log(f"{prec}: slices [0, {min(b + 16, block)}) done, {time.perf_counter() - t0:.1f} s")
+        sec = time.perf_counter() - t0
+        results[prec] = {"block_s": sec, "per_slice_s": sec / block,
+                         "extrapolated_full_s": sec * n_slices / block,
+                         "extrapolated_amplitudes_per_s": len(strings) / (sec * n_slices / block),
+                         "plan_s": t_plan, "workspace_gib": st["workspace_bytes"] / 2**30,
+                         "oracle_partials": parity,
+                         "cmacs_per_slice_block_avg": st["cmacs_full"] / n_slices}
+        plan.close()
+        del amps
+        torch.cuda.empty_cache()
+    head = results[precs[0]]
+    out = {
+        "metric": "amplitudes/sec (53-qubit share: slice block, extrapolated to all slices)",
+        "value": head["extrapolated_amplitudes_per_s"], "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 * head["block_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[precs[0]], "data": "synthetic",
+        "config": {"workload": f"{SHARE53}: 53 qubits (6x9 grid minus (0, 4)), 14 cycles, 3*10^5 "
+                               f"uniform strings, 2^{len(fx['sliced'])} slices, block of {block}",
+                   "slices": n_slices, "block": block},
+        "forms": results, "plan": fx["info"],
     }
     print(json.dumps(out), flush=True)
     return 0

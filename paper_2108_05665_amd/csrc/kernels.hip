@@ -252,6 +252,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //      the operand re-fetch of the 64 x 64 tile per MFMA)
 //   5: 128 x 128, eight waves with double-buffered LDS (split forms only,
 //      k_contract_split_db)
+//   6: 128 x 128, four waves of 64 x 64 on operands converted once into
+//      hi/lo planes (split forms only, k_presplit + k_contract_planes)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -297,6 +299,12 @@ struct Tile<4> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 2; };
 // the entry gives its shape to the shared epilogue and tile map.)
 template <>
 struct Tile<5> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 4; };
+// (Tile 6, 128 x 128 on plane-format operands, is k_contract_planes' own
+// layout; its epilogue writes half tiles, whose shape is entry 7.)
+template <>
+struct Tile<6> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 2; };
+template <>
+struct Tile<7> { static constexpr int BM = 64, BN = 128, MF = 32, WM = 2; };
 
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
@@ -1225,6 +1233,203 @@ __global__ void __launch_bounds__(512) k_contract_split_db(ContractArgs g) {
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
 }
 
+// ---------------------------------------------------------------------------
+// Plane-format split contraction (tile 6).  A pre-pass converts each operand
+// table once into hi/lo planes (k_presplit), so that the GEMM stages plain
+// 16-byte copies instead of re-splitting every element in every tile that
+// reads it.  Plane layout of an operand with K = 2^kb complex per row: row r,
+// slab j (complex j TK .. j TK + TK - 1) is one contiguous block of
+// 4 * TK halves: hi re, hi im, lo re, lo im, TK halves each (the FP16 form
+// scaled by 2^e as in k_contract_split).  A thread of k_presplit converts
+// four consecutive complex of a row.
+constexpr int kPlaneTK = 16;
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_presplit(const float2* src, int64_t rows, int kb,
+                                                  const unsigned long long* amax, int amax_n,
+                                                  uint16_t* dst) {
+  int e = 0;
+  if constexpr (PREC == 1) e = fp16_scale_exp(amax, amax_n);
+  const float s = ldexpf(1.f, e);
+  const int64_t K = int64_t(1) << kb;
+  const int64_t groups = (rows << kb) >> 2;  // four complex each
+  for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < groups;
+       gi += int64_t(gridDim.x) * 256) {
+    const int64_t c0 = gi << 2;              // first complex (flat index)
+    const int64_t r = c0 >> kb, k = c0 & (K - 1);
+    const float4 x = reinterpret_cast<const float4*>(src)[2 * gi];
+    const float4 y = reinterpret_cast<const float4*>(src)[2 * gi + 1];
+    uint16_t* at = dst + (r << (kb + 2)) + (k / kPlaneTK) * (4 * kPlaneTK) + (k % kPlaneTK);
+    split_store4<PREC>(x, y, s, at, kPlaneTK);
+  }
+}
+
+// The GEMM on plane-format operands: 128 x 128 tiles, four waves (2 x 2),
+// each a 64 x 64 block quad with two accumulators per 32 x 32 block; K slabs
+// of 16 complex.  Operand slabs go from global memory straight into LDS
+// (global_load_lds, 16 bytes per lane: each load instruction of a wave
+// fills 1 KB of LDS, eight rows of 128 bytes), double-buffered: the loads
+// of slab j + 1 are in flight while the MFMAs consume slab j, with one
+// barrier per slab.  Inside a 128-byte row the eight 16-byte chunks (hi re,
+// hi im, lo re, lo im; two each) sit at chunk position c ^ (row & 7), so
+// that the fragment reads of eight consecutive rows hit distinct banks.
+// The epilogue writes half tiles (64 rows) through LDS, so that two
+// workgroups share a CU.  Needs K >= 16 and no split K.
+template <int PREC>
+__global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
+  constexpr int BM = 128, BN = 128, TK = kPlaneTK;
+  constexpr int ROW_B = 8 * TK;                  // bytes of one row slab (128)
+  constexpr int OP_B = BM * ROW_B;               // bytes of one operand slab (16 KB)
+  constexpr int BUF_B = 2 * OP_B;                // A and B
+  constexpr int MAIN_F = 2 * BUF_B / 4;          // floats: two buffers
+  constexpr int HALF = 64;                       // epilogue rows per pass
+  constexpr int EPI_F = HALF * (BN + 1) * 2;
+  constexpr int LDS_F = MAIN_F > EPI_F ? MAIN_F : EPI_F;
+  constexpr int LOADS = OP_B / (4 * 1024);       // load instructions per wave and operand (4)
+  typedef float accv __attribute__((ext_vector_type(16)));
+  __shared__ __attribute__((aligned(1024))) float smem[LDS_F];
+  __shared__ int64_t dep_m_lo[HALF];
+  __shared__ int64_t dep_n_lo[BN];
+  char* lds = reinterpret_cast<char*>(smem);
+  float2* Ct = reinterpret_cast<float2*>(smem);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // rows 64 wm .., columns 64 wn ..
+  const TileMap<BM, BN> tmap(g);
+  const int64_t tiles = tmap.tiles;
+  const int64_t per_xcd = (tiles + 7) / 8;
+  const int64_t walk = per_xcd * 8;
+  const int nslabs = int((int64_t(1) << g.kb) / TK);
+  const uint64_t row_bytes = uint64_t(8) << g.kb;  // 4 planes x K halves
+
+  int eA = 0, eB = 0;
+  if constexpr (PREC == 1) {
+    eA = fp16_scale_exp(g.amaxA, g.amax_nA);
+    eB = fp16_scale_exp(g.amaxB, g.amax_nB);
+  }
+  const float s_out = ldexpf(1.f, -(eA + eB));
+  float amax = 0.f;
+
+  int r_tid = 0, c_tid = 0;
+  epilogue_setup<7>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
+  __syncthreads();
+
+  auto item_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
+  auto next_p = [&](int64_t p) -> int64_t {
+    for (p += gridDim.x; p < walk; p += gridDim.x)
+      if (item_of(p) < tiles) return p;
+    return walk;
+  };
+
+  const char* Ap = reinterpret_cast<const char*>(g.Ap);
+  const char* Bp = reinterpret_cast<const char*>(g.Bp);
+  // Lane l of load i of wave w fills LDS bytes 16 l of the 1 KB block
+  // 4 i + w: row (4 i + w) 8 + l / 8, position l % 8, i.e. chunk
+  // (l % 8) ^ (row % 8) of that row.
+  const int lrow = lane >> 3, lpos = lane & 7;
+  auto issue = [&](const TileOrigin& o, int j, int buf) {
+    const int64_t la = o.row_end - o.row0 - 1, lb = o.col_end - o.col0 - 1;
+    const char* baseA = Ap + uint64_t(o.row0) * row_bytes + uint64_t(j) * ROW_B;
+    const char* baseB = Bp + uint64_t(o.col0) * row_bytes + uint64_t(j) * ROW_B;
+    char* dst = lds + buf * BUF_B;
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int blk = 4 * i + wave, r = 8 * blk + lrow;
+      const int64_t ra = r < la ? r : la, rb = r < lb ? r : lb;
+      const int ch = lpos ^ (r & 7);
+      __builtin_amdgcn_global_load_lds(baseA + uint64_t(ra) * row_bytes + 16 * ch,
+                                       (__attribute__((address_space(3))) void*)(dst + 1024 * blk), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(baseB + uint64_t(rb) * row_bytes + 16 * ch,
+                                       (__attribute__((address_space(3))) void*)(dst + OP_B + 1024 * blk), 16, 0, 0);
+    }
+  };
+  // Fragment (row r, chunk c) of an operand slab at `base`.
+  auto frag = [&](const char* base, int r, int c) -> u32x4 {
+    return *reinterpret_cast<const u32x4*>(base + r * ROW_B + 16 * (c ^ (r & 7)));
+  };
+
+  int64_t p = blockIdx.x;
+  if (p < walk && item_of(p) >= tiles) p = next_p(p);
+  const int li = lane & 31, lg = lane >> 5;
+  while (p < walk) {
+    const TileOrigin o = tmap.at(g, item_of(p));
+    const int64_t pn = next_p(p);
+    accv acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc_re[fm][fn][v] = acc_im[fm][fn][v] = 0.f;
+
+    issue(o, 0, 0);
+    for (int j = 0; j < nslabs; ++j) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of slab j have landed
+      __syncthreads();                // everyone's have; slab j - 1's buffer is free
+      if (j + 1 < nslabs) issue(o, j + 1, (j + 1) & 1);
+      const char* bufA = lds + (j & 1) * BUF_B;
+      const char* bufB = bufA + OP_B;
+      u32x4 ar[2][4];
+#pragma unroll
+      for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) ar[fm][pl] = frag(bufA, wm * 64 + fm * 32 + li, 2 * pl + lg);
+#pragma unroll
+      for (int fn = 0; fn < 2; ++fn) {
+        const int rb = wn * 64 + fn * 32 + li;
+        const u32x4 brh = frag(bufB, rb, lg), bih = frag(bufB, rb, 2 + lg);
+        const u32x4 brl = frag(bufB, rb, 4 + lg), bil = frag(bufB, rb, 6 + lg);
+        const u32x4 nbih = bih ^ 0x80008000u, nbil = bil ^ 0x80008000u;
+#pragma unroll
+        for (int fm = 0; fm < 2; ++fm) {
+#define XEB_MMA(acc, x, y) acc = mma_split<32, PREC>(x, y, acc)
+          XEB_MMA(acc_re[fm][fn], ar[fm][0], brh);
+          XEB_MMA(acc_im[fm][fn], ar[fm][0], bih);
+          XEB_MMA(acc_re[fm][fn], ar[fm][1], nbih);
+          XEB_MMA(acc_im[fm][fn], ar[fm][1], brh);
+          XEB_MMA(acc_re[fm][fn], ar[fm][0], brl);
+          XEB_MMA(acc_im[fm][fn], ar[fm][0], bil);
+          XEB_MMA(acc_re[fm][fn], ar[fm][1], nbil);
+          XEB_MMA(acc_im[fm][fn], ar[fm][1], brl);
+          XEB_MMA(acc_re[fm][fn], ar[fm][2], brh);
+          XEB_MMA(acc_im[fm][fn], ar[fm][2], bih);
+          XEB_MMA(acc_re[fm][fn], ar[fm][3], nbih);
+          XEB_MMA(acc_im[fm][fn], ar[fm][3], brh);
+#undef XEB_MMA
+        }
+      }
+    }
+    __syncthreads();  // every wave is done with both buffers
+
+    // Epilogue in two passes of 64 rows: the waves holding rows
+    // 64 h .. 64 h + 63 park them, then all threads write them out.
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
+#pragma unroll
+        for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int r = fm * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+              const int c = wn * 64 + fn * 32 + (lane & 31);
+              Ct[r * (BN + 1) + c] =
+                  make_float2(acc_re[fm][fn][v] * s_out, acc_im[fm][fn][v] * s_out);
+            }
+      }
+      __syncthreads();
+      amax = fmaxf(amax, epilogue_write<7>(g, Ct, o.row0 + HALF * h, o.col0, o.key, o.row_end,
+                                           o.col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      __syncthreads();
+    }
+    p = pn;
+  }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+}
+
 // Split-K chunk sum: partial[0] += partial[1] + ... + partial[ksplit - 1],
 // element by element in chunk order (deterministic), two complex per thread.
 __global__ void __launch_bounds__(256) k_splitk_sum(float4* partial, int64_t chunk_f4, int ksplit) {
@@ -1395,6 +1600,8 @@ unsigned persistent_grid(int64_t tiles) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_mfma<CFG, PREC, TKV, KG>, 256 * KG, 0);
     else if constexpr (CFG == 5)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split_db<PREC>, 512, 0);
+    else if constexpr (CFG == 6)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC>, 256, 0);
     else
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split<CFG, PREC, TKV, KG>, 256 * KG, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
@@ -1426,6 +1633,17 @@ void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t row
   else if constexpr (CFG == 5)
     launch(k_contract_split_db<PREC>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)), dim3(512),
            s, true, true, a);
+  else if constexpr (CFG == 6) {
+    // Both operands into plane format, then the GEMM.
+    const int64_t rowsA = a.nvarA << a.mb, rowsB = a.nvarB << a.nb;
+    const int64_t groupsA = (rowsA << a.kb) >> 2, groupsB = (rowsB << a.kb) >> 2;
+    launch(k_presplit<PREC>, dim3(grid_for(groupsA, 256) < 8192 ? grid_for(groupsA, 256) : 8192), dim3(256),
+           s, true, false, a.A, rowsA, int(a.kb), a.amaxA, a.amax_nA, a.Ap);
+    launch(k_presplit<PREC>, dim3(grid_for(groupsB, 256) < 8192 ? grid_for(groupsB, 256) : 8192), dim3(256),
+           s, false, false, a.B, rowsB, int(a.kb), a.amaxB, a.amax_nB, a.Bp);
+    launch(k_contract_planes<PREC>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(256), s, false,
+           true, a);
+  }
   else
     launch(k_contract_split<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
            dim3(256 * KG), s, true, true, a);
@@ -1467,6 +1685,8 @@ void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t ro
     launch_cfg<4, PREC, lo>(a, s, rowsA, rowsB);
   } else if (a.tile == 5) {
     if constexpr (PREC != 0) launch_cfg<5, PREC, 16>(a, s, rowsA, rowsB);
+  } else if (a.tile == 6) {
+    if constexpr (PREC != 0) launch_cfg<6, PREC, 16>(a, s, rowsA, rowsB);
   } else {
     if (a.tile == 3)
       launch_cfg<3, PREC, lo>(a, s, rowsA, rowsB);
@@ -1492,6 +1712,8 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   }
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
+  if (a.tile == 6 && (a.ksplit != 1 || a.kb < 4 || !a.Ap || !a.Bp))
+    throw std::invalid_argument("plane-format tiles need K >= 16, no split K and plane buffers");
   if (a.prec == 0)
     launch_prec<0>(a, s, rowsA, rowsB);
   else if (a.prec == 1)
@@ -1520,7 +1742,7 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
 }
 
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
-  if (tile == 5) return prec != 0 && tk == 16 && kg == 1;
+  if (tile == 5 || tile == 6) return prec != 0 && tk == 16 && kg == 1;
   if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
   if (tk == lo) return tile >= 0 && tile <= 4;
@@ -1541,20 +1763,20 @@ void prepare_mfma_launch(int prec) {
     (void)persistent_grid<0, 1, 32, 1>(1), (void)persistent_grid<1, 1, 32, 1>(1);
     (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
     (void)persistent_grid<3, 1, 32, 1>(1), (void)persistent_grid<4, 1, 32, 1>(1);
-    (void)persistent_grid<5, 1, 16, 1>(1);
+    (void)persistent_grid<5, 1, 16, 1>(1), (void)persistent_grid<6, 1, 16, 1>(1);
     (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
     (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
     (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
     (void)persistent_grid<3, 2, 32, 1>(1), (void)persistent_grid<4, 2, 32, 1>(1);
-    (void)persistent_grid<5, 2, 16, 1>(1);
+    (void)persistent_grid<5, 2, 16, 1>(1), (void)persistent_grid<6, 2, 16, 1>(1);
     (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128, 128};
-  static const int kBN[kMfmaTiles] = {64, 128, 256, 16, 128, 128};
+  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128, 128, 128};
+  static const int kBN[kMfmaTiles] = {64, 128, 256, 16, 128, 128, 128};
   const int t = tile >= 0 && tile < kMfmaTiles ? tile : 0;
   *bm = kBM[t];
   *bn = kBN[t];

@@ -94,6 +94,8 @@ void leaves_dfs(const std::vector<Node>& nodes, int t, std::vector<int>& out) {
 // least four K slabs (64 complex) per chunk.  With more tiles the extra
 // partial traffic and launches cost more than the added parallelism gains.
 constexpr int64_t kSplitBelowTiles = 64, kSplitItems = 256, kMinChunk = 64;
+// Largest plane-format operand room (tile 6) a plan reserves.
+constexpr uint64_t kMaxPlaneBytes = uint64_t(16) << 30;
 // Split-K partial room reserved for the autotuner's candidates.
 constexpr uint64_t kTunePartialBytes = uint64_t(32) << 20;
 
@@ -129,8 +131,14 @@ bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& n
   return false;
 }
 
+uint64_t planes_need(const Node& nd, int64_t nvarL, int64_t nvarR) {
+  const uint64_t a = ((uint64_t(nvarL) << nd.mb) * (uint64_t(8) << nd.kb) + 255) & ~uint64_t(255);
+  return a + (uint64_t(nvarR) << nd.nb) * (uint64_t(8) << nd.kb) + 256;
+}
+
 bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
                   int swapped, int ksplit, int keyed) {
+  if (tile == 6 && (nd.kb < 4 || ksplit != 1)) return false;
   const bool stacked = mfma_capable(nd, nvarL, nvarR, nb);
   if (stacked && !keyed) return true;
   return ksplit == 1 && nd.kb >= 1 && nd.kb <= 21 && mfma_keyed_fits(nd, tile, swapped) &&
@@ -147,6 +155,7 @@ void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb,
   nb.kg = kg;
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
+  if (tile == 6) bm = 64;  // (its epilogue writes half tiles of 64 rows)
   // Epilogue write order: tile bits sorted by the output position they feed;
   // bits that select keys come last (columns before rows).
   const int kmb = swapped ? nd.nb : nd.mb, knb = swapped ? nd.mb : nd.nb;
@@ -678,6 +687,27 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     p.off_partial = off;
     p.partial_bytes = align_up(partial);
     off += p.partial_bytes;
+    // Plane-format operands (tile 6): both children of the largest node that
+    // could run it, converted on each launch, up to kMaxPlaneBytes (or 1/8
+    // of the budget); larger nodes do not take tile 6.
+    const uint64_t plane_cap =
+        o.memory_budget ? std::min<uint64_t>(kMaxPlaneBytes, o.memory_budget / 8) : kMaxPlaneBytes;
+    uint64_t planes = 0;
+    if (o.precision != XEB_PREC_C64)
+      for (const Block& blk : blocks)
+        for (int T = L; T < nn; ++T) {
+          const Node& nd = p.nodes[T];
+          const NodeBlock& nb = blk.nodes[T - L];
+          const int64_t nl = p.nodes[nd.left].leaf ? p.nodes[nd.left].leaf_nvar : blk.nodes[nd.left - L].nvar;
+          const int64_t nr = p.nodes[nd.right].leaf ? p.nodes[nd.right].leaf_nvar : blk.nodes[nd.right - L].nvar;
+          if (nd.kb < 4 || nd.kb > 21 || !(mfma_capable(nd, nl, nr, nb) || mfma_keyed(nd, nl, nr, nb)))
+            continue;
+          const uint64_t need = planes_need(nd, nl, nr);
+          if (need <= plane_cap) planes = std::max(planes, need);
+        }
+    p.off_planes = off;
+    p.planes_bytes = planes;
+    off += planes;
     p.off_comp = off;
     off += align_up((uint64_t(k) << w) * 16);
     if (w > 0) {
@@ -1004,6 +1034,12 @@ ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
   }
   a.ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
   a.partial = reinterpret_cast<float2*>(ws + p->off_partial);
+  if (p->planes_bytes) {
+    // Row operand's planes first, the column operand's after them.
+    const uint64_t a_bytes = align_up((uint64_t(a.nvarA) << a.mb) * (uint64_t(8) << a.kb));
+    a.Ap = reinterpret_cast<uint16_t*>(ws + p->off_planes);
+    a.Bp = reinterpret_cast<uint16_t*>(ws + p->off_planes + a_bytes);
+  }
   a.pairs = nb.kernel == XEB_KERNEL_MFMA && nb.pair_mode == 1
                 ? reinterpret_cast<const int32_t*>(ws + nb.off_pairs)
                 : nullptr;

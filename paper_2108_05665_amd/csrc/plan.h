@@ -108,6 +108,8 @@ struct Plan {
   uint64_t off_amax = 0;       // dynamic: kAmaxSlots (epoch << 32 | bits) slots per node
   uint64_t off_partial = 0;    // dynamic: split-K partial tiles
   uint64_t partial_bytes = 0;  // their capacity (largest need, or the tuning reserve)
+  uint64_t off_planes = 0;     // dynamic: plane-format operands of a tile-6 launch
+  uint64_t planes_bytes = 0;   // their capacity (0: no node can run tile 6)
   bool capturing = false;      // launches are being captured: no event timing
   void* ws = nullptr;
   uint64_t ws_size = 0;
@@ -153,6 +155,9 @@ bool mfma_capable(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock&
 // with the given row operand (at most 4x padding).
 bool mfma_keyed_fits(const Node& nd, int tile, int swapped);
 bool mfma_keyed(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb);
+// Bytes of both operands of a node in plane format (tile 6), either child
+// first (the larger of the two orders).
+uint64_t planes_need(const Node& nd, int64_t nvarL, int64_t nvarR);
 // Whether the MFMA kernel can run the node in this configuration.
 bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
                   int swapped, int ksplit, int keyed = 0);

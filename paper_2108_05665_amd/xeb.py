@@ -396,6 +396,7 @@ class Plan:
         if self._h:
             _lib.xeb_plan_destroy(self._h)
             self._h = _P()
+        self.workspace = None  # the device memory goes back to torch's allocator
 
     def __del__(self):
         try:

@@ -1,0 +1,56 @@
+"""One GPU's share of the 53-qubit contraction at full size (6x9 grid minus
+site (0, 4), 14 cycles, 3 * 10^5 uniform strings, the plan fixture's tree and
+2^25 slices, compiled within 270 GiB): single-slice partial amplitudes of the
+first strings against the stored FP64 oracle values
+(tests/golden/share_53q_m14_partials.json, written by
+tests/golden/make_share53_partials.py from the oracle alone).  A partial
+slice block yields no amplitude (Appendix A, "Slicing"), so the partials are
+what is compared.  Bounds as for the other workloads: complex64 1e-5, split
+forms 1e-3 normwise.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from synth import config_circuit, config_bitstrings
+from paper_2108_05665_amd import xeb
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PLAN = os.path.join(ROOT, "tests", "data", "share_53q_m14_plan.json")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "share_53q_m14_partials.json")
+TOL = {"c64": 1e-5, "split_fp16": 1e-3, "split_bf16": 1e-3}
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "c64"])
+def test_share53_slice_partials_vs_oracle(precision):
+    with open(PLAN) as f:
+        fx = json.load(f)
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    assert gold["sliced_legs"] == fx["sliced"]
+    circ = config_circuit("share_53q_m14")
+    strings = config_bitstrings("share_53q_m14", circ.n_qubits)
+    assert [str(int(s)) for s in strings[: gold["n_strings"]]] == \
+        [x["string"] for x in gold["partials"] if x["sigma"] == gold["sigmas"][0]]
+    torch.cuda.empty_cache()
+    p = xeb.Plan(circ, strings, fx["children"], fx["sliced"], precision=precision,
+                 memory_budget=270 * 2**30)
+    assert p.stats()["n_sliced"] == len(fx["sliced"])
+    for sigma in gold["sigmas"]:
+        a = p.new_amps()
+        p.contract(a, sigma, sigma + 1)
+        torch.cuda.synchronize()
+        got = a[: gold["n_strings"]].cpu().numpy()
+        ref = np.array([complex(*x["partial"]) for x in gold["partials"] if x["sigma"] == sigma])
+        rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"{precision} slice {sigma}: normwise {rel:.2e}")
+        assert rel <= TOL[precision], (sigma, rel)
+        del a
+    p.close()
+    torch.cuda.empty_cache()
