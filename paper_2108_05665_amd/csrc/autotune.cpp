@@ -63,7 +63,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
     for (int sw = 0; sw < 2; ++sw)
       for (int tile = 0; tile < kMfmaTiles; ++tile) {
         if (!mfma_can_run(nd, nl, nr, nb, tile, sw, 1, 1)) continue;
-        if (tile == 6 && planes_need(nd, nl, nr) > p->planes_bytes) continue;
+        if ((tile == 6 || tile == 7) && planes_need(nd, nl, nr) > p->planes_bytes) continue;
         for (int tk = 16; tk <= 2 * lo; tk *= 2)
           for (int kg = 1; kg <= 2; ++kg)
             if (mfma_variant_allowed(tile, p->opt.precision, tk, kg) && !(tk > lo && K < tk) &&
@@ -77,7 +77,7 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
     const double rows = double(sw ? nr : nl) * std::ldexp(1.0, sw ? nd.nb : nd.mb);
     const double cols = double(sw ? nl : nr) * std::ldexp(1.0, sw ? nd.mb : nd.nb);
     for (int tile = 0; tile < kMfmaTiles; ++tile) {
-      if (tile == 3 || (tile == 6 && planes_need(nd, nl, nr) > p->planes_bytes)) continue;
+      if (tile == 3 || ((tile == 6 || tile == 7) && planes_need(nd, nl, nr) > p->planes_bytes)) continue;
       int bm = 0, bn = 0;
       mfma_tile_shape(tile, &bm, &bn);
       const double padded = std::ceil(rows / bm) * bm * std::ceil(cols / bn) * bn *
@@ -149,7 +149,7 @@ void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
            "the MFMA kernel cannot run the node so (no pair table, or keys smaller than the "
            "tile, or split K on the keyed form)");
     if (partial_need(nd, nl, nr, c) > p->partial_bytes) fail(XEB_EINVAL, "split-K room exceeded");
-    if (c.kernel == XEB_KERNEL_MFMA && c.tile == 6 && planes_need(nd, nl, nr) > p->planes_bytes)
+    if (c.kernel == XEB_KERNEL_MFMA && (c.tile == 6 || c.tile == 7) && planes_need(nd, nl, nr) > p->planes_bytes)
       fail(XEB_EINVAL, "plane-format room exceeded (the node is too large for tile 6)");
   }
   for (Block& blk : p->blocks) {
@@ -239,7 +239,7 @@ AutotuneReport autotune_plan(Plan* p, int reps, hipStream_t stream) {
       if (c.kernel == XEB_KERNEL_MFMA && !mfma_can_run(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.keyed))
         c = kGeneric;
       if (c.kernel == XEB_KERNEL_MFMA && partial_need(nd, nl, nr, c) > p->partial_bytes) c.ksplit = 1;
-      if (c.kernel == XEB_KERNEL_MFMA && c.tile == 6 && planes_need(nd, nl, nr) > p->planes_bytes)
+      if (c.kernel == XEB_KERNEL_MFMA && (c.tile == 6 || c.tile == 7) && planes_need(nd, nl, nr) > p->planes_bytes)
         c = kGeneric;
       apply(nd, nl, nr, nb, c);
     }

@@ -42,7 +42,8 @@ struct ContractArgs {
   int32_t swapped;       // MFMA: rows are R's variants (A <- R, B <- L)
   int32_t tile;          // MFMA tile: 0 = 64 x 64, 1 = 32 x 128, 2 = 16 x 256, 3 = 64 x 16, 4 = 128 x 128,
                          // 5 = 128 x 128 on eight waves (split forms),
-                         // 6 = 128 x 128 on plane-format operands (split forms)
+                         // 6 = 128 x 128 on plane-format operands (split forms),
+                         // 7 = 256 x 128 on plane-format operands (split forms)
   int32_t tk;            // MFMA K slab (complex per LDS stage), see mfma_variant_allowed
   int32_t kg;            // MFMA K groups of four waves per workgroup (1 or 2)
   BitMap mapM;            // output bit positions of the row index's bits
@@ -92,14 +93,15 @@ void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 // them and writes T.
 void launch_contract_mfma(const ContractArgs& a, hipStream_t s);
 void launch_splitk_reduce(const ContractArgs& a, hipStream_t s);
-constexpr int kMfmaTiles = 7;  // tile shapes 0..6 (see mfma_tile_shape)
+constexpr int kMfmaTiles = 8;  // tile shapes 0..7 (see mfma_tile_shape)
 void mfma_tile_shape(int tile, int* bm, int* bn);
 // MFMA variants that are built: K slab complex64 16 (all tiles) or 32
 // (64 x 64, 32 x 128), split forms 32 (all tiles) or 64 (64 x 64); two K
 // groups (kg = 2, 512 threads) on the 64 x 64 tile only.  Tile 4 is 128 x 128;
 // tile 5 is 128 x 128 with eight waves and double-buffered LDS, split forms
 // only, K slab 16; tile 6 is 128 x 128 on operands converted once into hi/lo
-// planes (split forms, K slab 16, K >= 16, no split K).
+// planes (split forms, K slab 16, K >= 16, no split K); tile 7 the same at
+// 256 x 128 with eight waves.
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg);
 int mfma_default_slab(int prec);
 // Tiles of an MFMA contraction with rowsA x rowsB outputs on tile shape `tile`.

@@ -254,6 +254,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //      k_contract_split_db)
 //   6: 128 x 128, four waves of 64 x 64 on operands converted once into
 //      hi/lo planes (split forms only, k_presplit + k_contract_planes)
+//   7: 256 x 128, eight waves of 64 x 64 on plane-format operands, a ring
+//      of three LDS buffers (split forms only)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -305,6 +307,9 @@ template <>
 struct Tile<6> { static constexpr int BM = 128, BN = 128, MF = 32, WM = 2; };
 template <>
 struct Tile<7> { static constexpr int BM = 64, BN = 128, MF = 32, WM = 2; };
+// (Tile 7 of the API, 256 x 128 on plane-format operands with eight waves.)
+template <>
+struct Tile<8> { static constexpr int BM = 256, BN = 128, MF = 32, WM = 4; };
 
 template <int CFG, int PREC, int TKV = 16>
 struct TileInfo {
@@ -1240,10 +1245,13 @@ __global__ void __launch_bounds__(512) k_contract_split_db(ContractArgs g) {
 // reads it.  Plane layout of an operand with K = 2^kb complex per row: row r,
 // slab j (complex j TK .. j TK + TK - 1) is one contiguous block of
 // 4 * TK halves: hi re, hi im, lo re, lo im, TK halves each (the FP16 form
-// scaled by 2^e as in k_contract_split).  A thread of k_presplit converts
-// four consecutive complex of a row.
+// scaled by 2^e as in k_contract_split).
 constexpr int kPlaneTK = 16;
 
+// Lane l of the conversion writes 16-byte chunk l % 8 (plane (l % 8) / 2,
+// complex 8 ((l % 8) % 2) .. + 7 of the slab) of row slab l / 8, so that a
+// wave stores 1 KB of contiguous output; the four lanes that need the same
+// eight complex inputs read them through the cache.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_presplit(const float2* src, int64_t rows, int kb,
                                                   const unsigned long long* amax, int amax_n,
@@ -1251,41 +1259,52 @@ __global__ void __launch_bounds__(256) k_presplit(const float2* src, int64_t row
   int e = 0;
   if constexpr (PREC == 1) e = fp16_scale_exp(amax, amax_n);
   const float s = ldexpf(1.f, e);
-  const int64_t K = int64_t(1) << kb;
-  const int64_t groups = (rows << kb) >> 2;  // four complex each
-  for (int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x; gi < groups;
-       gi += int64_t(gridDim.x) * 256) {
-    const int64_t c0 = gi << 2;              // first complex (flat index)
-    const int64_t r = c0 >> kb, k = c0 & (K - 1);
-    const float4 x = reinterpret_cast<const float4*>(src)[2 * gi];
-    const float4 y = reinterpret_cast<const float4*>(src)[2 * gi + 1];
-    uint16_t* at = dst + (r << (kb + 2)) + (k / kPlaneTK) * (4 * kPlaneTK) + (k % kPlaneTK);
-    split_store4<PREC>(x, y, s, at, kPlaneTK);
+  const int64_t chunks = (rows << kb) >> 1;  // 16-byte output chunks (8 per 16 complex)
+  for (int64_t ci = int64_t(blockIdx.x) * 256 + threadIdx.x; ci < chunks;
+       ci += int64_t(gridDim.x) * 256) {
+    const int c = int(ci & 7);
+    const int plane = c >> 1;  // 0 hi re, 1 hi im, 2 lo re, 3 lo im
+    const int64_t first = ((ci >> 3) << 4) + 8 * (c & 1);  // flat index of the first complex
+    const float4* in = reinterpret_cast<const float4*>(src + first);
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 x = in[q];  // two complex
+      uint32_t h0, l0, h1, l1;
+      split2<PREC>(((plane & 1) ? x.y : x.x) * s, h0, l0);
+      split2<PREC>(((plane & 1) ? x.w : x.z) * s, h1, l1);
+      w[q] = (plane < 2) ? (h0 | (h1 << 16)) : (l0 | (l1 << 16));
+    }
+    reinterpret_cast<u32x4*>(dst)[ci] = u32x4{w[0], w[1], w[2], w[3]};
   }
 }
 
-// The GEMM on plane-format operands: 128 x 128 tiles, four waves (2 x 2),
-// each a 64 x 64 block quad with two accumulators per 32 x 32 block; K slabs
-// of 16 complex.  Operand slabs go from global memory straight into LDS
-// (global_load_lds, 16 bytes per lane: each load instruction of a wave
-// fills 1 KB of LDS, eight rows of 128 bytes), double-buffered: the loads
-// of slab j + 1 are in flight while the MFMAs consume slab j, with one
+// The GEMM on plane-format operands.  WMT x 2 waves, each a 64 x 64 block
+// quad (two 32 x 32 blocks per side, two accumulators per block), so the
+// tile is (64 WMT) x 128: tile 6 takes WMT = 2 (128 x 128, four waves, two
+// workgroups per CU), tile 7 WMT = 4 (256 x 128, eight waves).  K slabs of
+// 16 complex go from global memory straight into LDS (global_load_lds, 16
+// bytes per lane: each load instruction of a wave fills 1 KB of LDS, eight
+// rows of 128 bytes) through a ring of NBUF buffers: while the MFMAs consume
+// slab j, the loads of slabs j + 1 .. j + NBUF - 1 are in flight, with one
 // barrier per slab.  Inside a 128-byte row the eight 16-byte chunks (hi re,
 // hi im, lo re, lo im; two each) sit at chunk position c ^ (row & 7), so
 // that the fragment reads of eight consecutive rows hit distinct banks.
-// The epilogue writes half tiles (64 rows) through LDS, so that two
-// workgroups share a CU.  Needs K >= 16 and no split K.
-template <int PREC>
-__global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
-  constexpr int BM = 128, BN = 128, TK = kPlaneTK;
+// The epilogue writes 64-row slices of the tile through LDS.  Needs K >= 16
+// and no split K.
+template <int PREC, int WMT, int NBUF>
+__global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes(ContractArgs g) {
+  constexpr int BM = 64 * WMT, BN = 128, TK = kPlaneTK;
+  constexpr int NT = 128 * WMT, NW = 2 * WMT;    // threads, waves
   constexpr int ROW_B = 8 * TK;                  // bytes of one row slab (128)
-  constexpr int OP_B = BM * ROW_B;               // bytes of one operand slab (16 KB)
-  constexpr int BUF_B = 2 * OP_B;                // A and B
-  constexpr int MAIN_F = 2 * BUF_B / 4;          // floats: two buffers
+  constexpr int A_B = BM * ROW_B, B_B = BN * ROW_B;
+  constexpr int BUF_B = A_B + B_B;
+  constexpr int MAIN_F = NBUF * BUF_B / 4;       // floats: the ring
   constexpr int HALF = 64;                       // epilogue rows per pass
   constexpr int EPI_F = HALF * (BN + 1) * 2;
   constexpr int LDS_F = MAIN_F > EPI_F ? MAIN_F : EPI_F;
-  constexpr int LOADS = OP_B / (4 * 1024);       // load instructions per wave and operand (4)
+  constexpr int LA = A_B / 1024 / NW, LB = B_B / 1024 / NW;  // loads per wave and slab
+  static_assert(LA * NW * 1024 == A_B && LB * NW * 1024 == B_B, "whole 1 KB blocks per wave");
   typedef float accv __attribute__((ext_vector_type(16)));
   __shared__ __attribute__((aligned(1024))) float smem[LDS_F];
   __shared__ int64_t dep_m_lo[HALF];
@@ -1313,7 +1332,7 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
   float amax = 0.f;
 
   int r_tid = 0, c_tid = 0;
-  epilogue_setup<7>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
+  epilogue_setup<7, NT>(g, dep_m_lo, dep_n_lo, r_tid, c_tid);
   __syncthreads();
 
   auto item_of = [&](int64_t p) -> int64_t { return (p & 7) * per_xcd + (p >> 3); };
@@ -1325,9 +1344,8 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
 
   const char* Ap = reinterpret_cast<const char*>(g.Ap);
   const char* Bp = reinterpret_cast<const char*>(g.Bp);
-  // Lane l of load i of wave w fills LDS bytes 16 l of the 1 KB block
-  // 4 i + w: row (4 i + w) 8 + l / 8, position l % 8, i.e. chunk
-  // (l % 8) ^ (row % 8) of that row.
+  // Lane l of the wave's load into 1 KB block b fills its bytes 16 l: row
+  // 8 b + l / 8, position l % 8, i.e. chunk (l % 8) ^ (row % 8) of the row.
   const int lrow = lane >> 3, lpos = lane & 7;
   auto issue = [&](const TileOrigin& o, int j, int buf) {
     const int64_t la = o.row_end - o.row0 - 1, lb = o.col_end - o.col0 - 1;
@@ -1335,20 +1353,30 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
     const char* baseB = Bp + uint64_t(o.col0) * row_bytes + uint64_t(j) * ROW_B;
     char* dst = lds + buf * BUF_B;
 #pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
-      const int blk = 4 * i + wave, r = 8 * blk + lrow;
-      const int64_t ra = r < la ? r : la, rb = r < lb ? r : lb;
-      const int ch = lpos ^ (r & 7);
-      __builtin_amdgcn_global_load_lds(baseA + uint64_t(ra) * row_bytes + 16 * ch,
+    for (int i = 0; i < LA; ++i) {
+      const int blk = NW * i + wave, r = 8 * blk + lrow;
+      const int64_t ra = r < la ? r : la;
+      __builtin_amdgcn_global_load_lds(baseA + uint64_t(ra) * row_bytes + 16 * (lpos ^ (r & 7)),
                                        (__attribute__((address_space(3))) void*)(dst + 1024 * blk), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(baseB + uint64_t(rb) * row_bytes + 16 * ch,
-                                       (__attribute__((address_space(3))) void*)(dst + OP_B + 1024 * blk), 16, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int blk = NW * i + wave, r = 8 * blk + lrow;
+      const int64_t rb = r < lb ? r : lb;
+      __builtin_amdgcn_global_load_lds(baseB + uint64_t(rb) * row_bytes + 16 * (lpos ^ (r & 7)),
+                                       (__attribute__((address_space(3))) void*)(dst + A_B + 1024 * blk), 16, 0, 0);
     }
   };
   // Fragment (row r, chunk c) of an operand slab at `base`.
   auto frag = [&](const char* base, int r, int c) -> u32x4 {
     return *reinterpret_cast<const u32x4*>(base + r * ROW_B + 16 * (c ^ (r & 7)));
   };
+  // s_waitcnt: this wave's loads of all but the last n slabs issued have
+  // landed (vmcnt = n (LA + LB); expcnt and lgkmcnt not waited on).
+  constexpr int LPS = LA + LB;
+  constexpr int WAIT_KEEP = (NBUF - 2) * LPS;
+  static_assert(WAIT_KEEP < 64, "vmcnt field");
+  constexpr int WAIT_IMM = (WAIT_KEEP & 15) | ((WAIT_KEEP >> 4) << 14) | (7 << 4) | (15 << 8);
 
   int64_t p = blockIdx.x;
   if (p < walk && item_of(p) >= tiles) p = next_p(p);
@@ -1364,13 +1392,19 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc_re[fm][fn][v] = acc_im[fm][fn][v] = 0.f;
 
-    issue(o, 0, 0);
+#pragma unroll
+    for (int q = 0; q < NBUF - 1; ++q)
+      if (q < nslabs) issue(o, q, q);
     for (int j = 0; j < nslabs; ++j) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of slab j have landed
-      __syncthreads();                // everyone's have; slab j - 1's buffer is free
-      if (j + 1 < nslabs) issue(o, j + 1, (j + 1) & 1);
-      const char* bufA = lds + (j & 1) * BUF_B;
-      const char* bufB = bufA + OP_B;
+      // This wave's loads of slab j have landed (later slabs may be in flight).
+      if (j + NBUF - 2 < nslabs)
+        __builtin_amdgcn_s_waitcnt(WAIT_IMM);
+      else
+        __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();  // everyone's have; slab j - 1's buffer is free
+      if (j + NBUF - 1 < nslabs) issue(o, j + NBUF - 1, (j + NBUF - 1) % NBUF);
+      const char* bufA = lds + (j % NBUF) * BUF_B;
+      const char* bufB = bufA + A_B;
       u32x4 ar[2][4];
 #pragma unroll
       for (int fm = 0; fm < 2; ++fm)
@@ -1401,12 +1435,12 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
         }
       }
     }
-    __syncthreads();  // every wave is done with both buffers
+    __syncthreads();  // every wave is done with the ring
 
-    // Epilogue in two passes of 64 rows: the waves holding rows
-    // 64 h .. 64 h + 63 park them, then all threads write them out.
+    // Epilogue in passes of 64 rows: the waves holding rows 64 h .. 64 h + 63
+    // park them, then all threads write them out.
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < WMT; ++h) {
       if (wm == h) {
 #pragma unroll
         for (int fm = 0; fm < 2; ++fm)
@@ -1421,8 +1455,8 @@ __global__ void __launch_bounds__(256, 2) k_contract_planes(ContractArgs g) {
             }
       }
       __syncthreads();
-      amax = fmaxf(amax, epilogue_write<7>(g, Ct, o.row0 + HALF * h, o.col0, o.key, o.row_end,
-                                           o.col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
+      amax = fmaxf(amax, epilogue_write<7, NT>(g, Ct, o.row0 + HALF * h, o.col0, o.key, o.row_end,
+                                               o.col_end, dep_m_lo, dep_n_lo, r_tid, c_tid));
       __syncthreads();
     }
     p = pn;
@@ -1601,7 +1635,9 @@ unsigned persistent_grid(int64_t tiles) {
     else if constexpr (CFG == 5)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split_db<PREC>, 512, 0);
     else if constexpr (CFG == 6)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC>, 256, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC, 2, 2>, 256, 0);
+    else if constexpr (CFG == 8)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC, 4, 3>, 512, 0);
     else
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split<CFG, PREC, TKV, KG>, 256 * KG, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
@@ -1633,16 +1669,20 @@ void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t row
   else if constexpr (CFG == 5)
     launch(k_contract_split_db<PREC>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)), dim3(512),
            s, true, true, a);
-  else if constexpr (CFG == 6) {
+  else if constexpr (CFG == 6 || CFG == 8) {
     // Both operands into plane format, then the GEMM.
     const int64_t rowsA = a.nvarA << a.mb, rowsB = a.nvarB << a.nb;
-    const int64_t groupsA = (rowsA << a.kb) >> 2, groupsB = (rowsB << a.kb) >> 2;
-    launch(k_presplit<PREC>, dim3(grid_for(groupsA, 256) < 8192 ? grid_for(groupsA, 256) : 8192), dim3(256),
+    const int64_t chunksA = (rowsA << a.kb) >> 1, chunksB = (rowsB << a.kb) >> 1;
+    launch(k_presplit<PREC>, dim3(grid_for(chunksA, 256) < 16384 ? grid_for(chunksA, 256) : 16384), dim3(256),
            s, true, false, a.A, rowsA, int(a.kb), a.amaxA, a.amax_nA, a.Ap);
-    launch(k_presplit<PREC>, dim3(grid_for(groupsB, 256) < 8192 ? grid_for(groupsB, 256) : 8192), dim3(256),
+    launch(k_presplit<PREC>, dim3(grid_for(chunksB, 256) < 16384 ? grid_for(chunksB, 256) : 16384), dim3(256),
            s, false, false, a.B, rowsB, int(a.kb), a.amaxB, a.amax_nB, a.Bp);
-    launch(k_contract_planes<PREC>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(256), s, false,
-           true, a);
+    if constexpr (CFG == 6)
+      launch(k_contract_planes<PREC, 2, 2>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(256), s,
+             false, true, a);
+    else
+      launch(k_contract_planes<PREC, 4, 3>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(512), s,
+             false, true, a);
   }
   else
     launch(k_contract_split<CFG, PREC, TKV, KG>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles * a.ksplit)),
@@ -1687,6 +1727,8 @@ void launch_prec(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t ro
     if constexpr (PREC != 0) launch_cfg<5, PREC, 16>(a, s, rowsA, rowsB);
   } else if (a.tile == 6) {
     if constexpr (PREC != 0) launch_cfg<6, PREC, 16>(a, s, rowsA, rowsB);
+  } else if (a.tile == 7) {
+    if constexpr (PREC != 0) launch_cfg<8, PREC, 16>(a, s, rowsA, rowsB);
   } else {
     if (a.tile == 3)
       launch_cfg<3, PREC, lo>(a, s, rowsA, rowsB);
@@ -1712,7 +1754,7 @@ void launch_contract_mfma(const ContractArgs& a, hipStream_t s) {
   }
   if (a.ksplit < 1 || (a.ksplit > 1 && (!a.partial || (int64_t(1) << a.kb) % (int64_t(a.ksplit) * a.tk))))
     throw std::invalid_argument("split K needs a partial buffer and chunks of whole K slabs");
-  if (a.tile == 6 && (a.ksplit != 1 || a.kb < 4 || !a.Ap || !a.Bp))
+  if ((a.tile == 6 || a.tile == 7) && (a.ksplit != 1 || a.kb < 4 || !a.Ap || !a.Bp))
     throw std::invalid_argument("plane-format tiles need K >= 16, no split K and plane buffers");
   if (a.prec == 0)
     launch_prec<0>(a, s, rowsA, rowsB);
@@ -1742,7 +1784,7 @@ void launch_splitk_reduce(const ContractArgs& a, hipStream_t s) {
 }
 
 bool mfma_variant_allowed(int tile, int prec, int tk, int kg) {
-  if (tile == 5 || tile == 6) return prec != 0 && tk == 16 && kg == 1;
+  if (tile >= 5) return prec != 0 && tk == 16 && kg == 1;
   if (kg != 1 && !(kg == 2 && tile == 0)) return false;
   const int lo = prec == 0 ? 16 : 32;
   if (tk == lo) return tile >= 0 && tile <= 4;
@@ -1764,19 +1806,21 @@ void prepare_mfma_launch(int prec) {
     (void)persistent_grid<2, 1, 32, 1>(1), (void)persistent_grid<0, 1, 64, 1>(1);
     (void)persistent_grid<3, 1, 32, 1>(1), (void)persistent_grid<4, 1, 32, 1>(1);
     (void)persistent_grid<5, 1, 16, 1>(1), (void)persistent_grid<6, 1, 16, 1>(1);
+    (void)persistent_grid<8, 1, 16, 1>(1);
     (void)persistent_grid<0, 1, 32, 2>(1), (void)persistent_grid<0, 1, 64, 2>(1);
   } else {
     (void)persistent_grid<0, 2, 32, 1>(1), (void)persistent_grid<1, 2, 32, 1>(1);
     (void)persistent_grid<2, 2, 32, 1>(1), (void)persistent_grid<0, 2, 64, 1>(1);
     (void)persistent_grid<3, 2, 32, 1>(1), (void)persistent_grid<4, 2, 32, 1>(1);
     (void)persistent_grid<5, 2, 16, 1>(1), (void)persistent_grid<6, 2, 16, 1>(1);
+    (void)persistent_grid<8, 2, 16, 1>(1);
     (void)persistent_grid<0, 2, 32, 2>(1), (void)persistent_grid<0, 2, 64, 2>(1);
   }
 }
 
 void mfma_tile_shape(int tile, int* bm, int* bn) {
-  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128, 128, 128};
-  static const int kBN[kMfmaTiles] = {64, 128, 256, 16, 128, 128, 128};
+  static const int kBM[kMfmaTiles] = {64, 32, 16, 64, 128, 128, 128, 256};
+  static const int kBN[kMfmaTiles] = {64, 128, 256, 16, 128, 128, 128, 128};
   const int t = tile >= 0 && tile < kMfmaTiles ? tile : 0;
   *bm = kBM[t];
   *bn = kBN[t];

@@ -138,7 +138,7 @@ uint64_t planes_need(const Node& nd, int64_t nvarL, int64_t nvarR) {
 
 bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
                   int swapped, int ksplit, int keyed) {
-  if (tile == 6 && (nd.kb < 4 || ksplit != 1)) return false;
+  if ((tile == 6 || tile == 7) && (nd.kb < 4 || ksplit != 1)) return false;
   const bool stacked = mfma_capable(nd, nvarL, nvarR, nb);
   if (stacked && !keyed) return true;
   return ksplit == 1 && nd.kb >= 1 && nd.kb <= 21 && mfma_keyed_fits(nd, tile, swapped) &&
@@ -155,7 +155,7 @@ void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb,
   nb.kg = kg;
   int bm = 0, bn = 0;
   mfma_tile_shape(tile, &bm, &bn);
-  if (tile == 6) bm = 64;  // (its epilogue writes half tiles of 64 rows)
+  if (tile == 6 || tile == 7) bm = 64;  // (their epilogues write 64-row slices)
   // Epilogue write order: tile bits sorted by the output position they feed;
   // bits that select keys come last (columns before rows).
   const int kmb = swapped ? nd.nb : nd.mb, knb = swapped ? nd.mb : nd.nb;

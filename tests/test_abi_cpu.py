@@ -276,7 +276,8 @@ def test_node_config_get_set_and_validation():
     assert (got["tile"], got["swapped"], got["k_slab"], got["k_groups"]) == (0, 1 - before["swapped"], 32, 2)
     ns = {x["node"]: x for x in p.all_node_stats()}[node]
     assert (ns["k_slab"], ns["k_groups"]) == (32, 2)
-    for bad in (dict(tile=6), dict(tile=-1), dict(tile=5), dict(tile=5, k_slab=32), dict(k_slab=64), dict(k_groups=3), dict(tile=2, k_groups=2),
+    for bad in (dict(tile=8), dict(tile=-1), dict(tile=5), dict(tile=5, k_slab=32), dict(tile=6),
+                dict(tile=7), dict(k_slab=64), dict(k_groups=3), dict(tile=2, k_groups=2),
                 dict(tile=3, k_groups=2), dict(tile=3, k_slab=32), dict(tile=4, k_slab=32),
                 dict(tile=4, k_groups=2),
                 dict(ksplit=3), dict(ksplit=1 << 7)):

@@ -446,11 +446,13 @@ def test_every_mfma_variant_vs_state_vector(precision):
 
 @pytest.mark.parametrize("precision,tile", [("c64", 4), ("split_fp16", 4), ("split_bf16", 4),
                                             ("split_fp16", 5), ("split_bf16", 5),
-                                            ("split_fp16", 6), ("split_bf16", 6)])
+                                            ("split_fp16", 6), ("split_bf16", 6),
+                                            ("split_fp16", 7), ("split_bf16", 7)])
 def test_wide_tile_vs_state_vector(precision, tile):
     """The 128x128 tiles (4: four 32x32 blocks per wave; 5: eight waves with
     double-buffered LDS; 6: plane-format operands loaded straight into LDS;
-    5 and 6 split forms only) forced on every MFMA-capable node,
+    7: the same at 256x128 with eight waves; 5-7 split forms only) forced on
+    every MFMA-capable node,
     unsplit, with split K, and in the keyed form where a key's product spans
     at least 64 x 64: amplitudes within the bound of the state vector, reruns
     bit-identical."""
@@ -459,7 +461,7 @@ def test_wide_tile_vs_state_vector(precision, tile):
     strings = prefix_bitstrings(20, 4000, 12, 5)
     ch, sl, _ = planner.plan(circ, strings, n_sliced=2, trials=6)
     ref = statevec.state_vector(circ)[strings.astype(np.int64)]
-    lo = 16 if precision == "c64" or tile in (5, 6) else 32
+    lo = 16 if precision == "c64" or tile >= 5 else 32
     p = xeb.Plan(circ, strings, ch, sl, precision=precision, stack_slices=1, **SMALL_MFMA)
     nodes = [ns for ns in p.all_node_stats() if ns["kernel"] == "mfma"]
     assert nodes
@@ -472,7 +474,7 @@ def test_wide_tile_vs_state_vector(precision, tile):
                 ks = 2
             if mode == "keyed":
                 rb, cb = (ns["n_bits"], ns["m_bits"]) if ns["swapped"] else (ns["m_bits"], ns["n_bits"])
-                keyed = 1 if rb >= 6 and cb >= 6 else 0
+                keyed = 1 if rb >= (7 if tile == 7 else 6) and cb >= 6 else 0
             try:
                 p.set_node_config(ns["node"], "mfma", tile=tile, swapped=ns["swapped"], ksplit=ks,
                                   k_slab=lo, k_groups=1, keyed=keyed)
@@ -487,7 +489,7 @@ def test_wide_tile_vs_state_vector(precision, tile):
         assert torch.equal(a, b)
         err = _rel(a.cpu().numpy(), ref)
         assert err <= tol, (mode, err)
-        assert used > 0 or (tile == 6 and mode == "split_k"), mode  # (tile 6 never splits K)
+        assert used > 0 or (tile >= 6 and mode == "split_k"), mode  # (tiles 6, 7 never split K)
 
 
 @pytest.mark.parametrize("precision", ["c64", "split_fp16", "split_bf16"])
