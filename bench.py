@@ -130,7 +130,11 @@ def roofline(prof: dict, prec: str) -> dict:
              "frac": gbs / HBM_PEAK_GBS}
     traffic = measured_traffic(prec)
     bytes_per_launch = mf["bytes"] / max(mf["launches"], 1)
-    r.update({"traffic": traffic, "kernel": "k_contract_mfma" if prec == "c64" else "k_contract_split",
+    # One launch of the split forms is a k_contract_split* dispatch, or the two
+    # k_presplit conversions and the k_contract_planes GEMM (one event pair).
+    kernel = ("k_contract_mfma" if prec == "c64"
+              else "split MFMA launch (k_contract_split*, or k_presplit x2 + k_contract_planes)")
+    r.update({"traffic": traffic, "kernel": kernel,
               "hbm_frac": gbs / HBM_PEAK_GBS,
               "mfma_issue_frac": issued_tflops / PEAK_TFLOPS[prec],
               "algorithmic_bytes_per_launch": bytes_per_launch,
