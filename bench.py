@@ -218,8 +218,8 @@ def main() -> int:
                          "share of the 53-qubit contraction (a block of slices)")
     ap.add_argument("--slice-block", type=int, default=256,
                     help="share53: slices contracted (a contiguous block from slice 0)")
-    ap.add_argument("--batch-budget-gib", type=float, default=6.0,
-                    help="batch32: HBM workspace budget per circuit")
+    ap.add_argument("--batch-budget-gib", type=float, default=None,
+                    help="batch32: HBM workspace budget per circuit (default: a 32nd of 270 GiB)")
     ap.add_argument("--batch-max-seconds", type=float, default=2.0,
                     help="batch32: circuits whose best plan is estimated above this many "
                          "seconds per full contraction are planned but left out of the run")
@@ -480,6 +480,8 @@ def main() -> int:
 
 
 BATCH_SLICINGS = (6, 8, 10, 12, 16)
+BATCH_HBM_GIB = 270.0  # of the 288 GB of HBM, what the batch's workspaces may take
+BATCH_MAX_STACK = 6
 
 
 def batch_workload(i: int):
@@ -504,7 +506,9 @@ def batch_main(args) -> int:
     listed with their estimates and left out of the launch."""
     import numpy as np
 
-    budget = int(args.batch_budget_gib * 2**30)
+    # One launch holds all 32 circuits, so all their workspaces are resident at
+    # once: each circuit's budget is a 32nd of the HBM left for workspaces.
+    budget = int((args.batch_budget_gib if args.batch_budget_gib else BATCH_HBM_GIB / 32) * 2**30)
     if args.plan_only:
         from paper_2108_05665_amd import planner, xeb
 
@@ -523,16 +527,24 @@ def batch_main(args) -> int:
                 if best is None or info["seconds"] < best["info"]["seconds"]:
                     best = {"i": i, "children": [[int(a), int(b)] for a, b in ch],
                             "sliced": [int(x) for x in sl], "info": info,
-                            "workspace_bytes": int(st["workspace_bytes"])}
+                            "workspace_bytes": int(st["workspace_bytes"]),
+                            "n_blocks": int(st["n_blocks"])}
             if best is None:
                 log(f"circuit {i}: no slicing in {BATCH_SLICINGS} fits {budget} bytes")
                 plans.append({"i": i, "included": False, "reason": "no plan within the budget"})
                 continue
+            # Stack the low slice bits as far as the budget allows without more
+            # string blocks (at most 2^6 slices per launch).
+            J, stj = planner.choose_stacking(circ, strings, best["children"], best["sliced"], budget,
+                                             max_stack=BATCH_MAX_STACK, max_blocks=best["n_blocks"])
+            best["stack_slices"] = J
+            if J:
+                best["workspace_bytes"] = int(stj["workspace_bytes"])
             best["included"] = best["info"]["seconds"] <= args.batch_max_seconds
             if not best["included"]:
                 best["reason"] = "estimated above --batch-max-seconds"
             log(f"circuit {i}: {circ.n_qubits} qubits, {sp['cycles']} cycles, k={sp['k']}, "
-                f"s={len(best['sliced'])}, estimated {best['info']['seconds']:.3f} s"
+                f"s={len(best['sliced'])}, J={J}, estimated {best['info']['seconds']:.3f} s"
                 f"{'' if best['included'] else ' (left out)'}")
             plans.append(best)
         with open(args.plan_only, "w") as f:
@@ -567,7 +579,7 @@ def batch_main(args) -> int:
                 continue
             sp, circ, strings = batch_workload(rec["i"])
             plan = xeb.Plan(circ, strings, rec["children"], rec["sliced"], precision=prec,
-                            memory_budget=saved["budget"])
+                            memory_budget=saved["budget"], stack_slices=rec.get("stack_slices", 0))
             if not args.no_autotune:
                 plan.autotune(reps=2)
             plans.append(plan)

@@ -48,6 +48,8 @@ extern "C" {
 #define XEB_EHIP (-3)    /* HIP runtime error; the message carries HIP's text */
 #define XEB_ESTATE (-4)  /* call out of order (e.g. contract before bind) */
 #define XEB_ELIMIT (-5)  /* a documented size limit exceeded (e.g. batch graph nodes) */
+#define XEB_EABORT (-6)  /* injected abort (xeb_options_t.abort_after_slices); the work
+                            done before it is kept and can be resumed */
 
 /* Opaque plan handle. */
 typedef struct xeb_plan* xeb_plan_t;
@@ -129,6 +131,12 @@ typedef struct {
                              the 2^w amplitudes of the strings that agree with it on
                              every other qubit; the strings' open bits select nothing
                              and only the XEB reads them.  Default 0. */
+  int64_t abort_after_slices; /* failure injection for stop / resume (slices are
+                             independent, Appendix A, "Slicing", so recovery means
+                             contracting the missing slice range): > 0 makes
+                             xeb_contract stop once this plan has contracted that many
+                             slices over all its calls and return XEB_EABORT (see there).
+                             0 = never (default). */
 } xeb_options_t;
 
 typedef struct {
@@ -149,6 +157,7 @@ typedef struct {
   int64_t n_blocks;          /* string blocks chosen by the dry run (1 = all strings at once) */
   int32_t n_stacked;         /* J of xeb_options_t.stack_slices */
   int32_t n_open;            /* w: open output qubits; amps hold k * 2^w values */
+  int64_t slices_done;       /* slices contracted by xeb_contract over the plan's life */
 } xeb_stats_t;
 
 #define XEB_KERNEL_GENERIC 0  /* per-element kernel (small or sparse nodes) */
@@ -166,7 +175,9 @@ typedef struct {
   int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
   int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256, 3 = 64x16,
                                 4 = 128x128, 5 = 128x128 on eight waves with double-
-                                buffered LDS (split forms) */
+                                buffered LDS (split forms), 6 = 128x128 and 7 = 256x128
+                                on operands converted to hi/lo planes first (split
+                                forms, K >= 16, room in the planes region) */
   int32_t ksplit;            /* MFMA: K chunks summed by a second kernel (1 = no split) */
   int32_t k_slab;            /* MFMA: complex K values staged per LDS step */
   int32_t k_groups;          /* MFMA: groups of four waves splitting K inside a workgroup */
@@ -271,7 +282,13 @@ int xeb_plan_bind_workspace(xeb_plan_t plan, void* dev_ptr, uint64_t bytes);
  * Within a call, a node whose slice bits do not change between consecutive
  * slices keeps its resident table instead of being contracted again; nothing
  * is carried from one call to the next.
- * Errors: XEB_EINVAL (range), XEB_ESTATE (no workspace), XEB_EHIP.
+ * With xeb_options_t.abort_after_slices = A > 0 and D slices contracted by
+ * earlier calls, a call whose range holds more than max(A - D, 0) slices
+ * contracts only its first max(A - D, 0) slices [begin, stop), folds them
+ * into amps as a complete call over [begin, stop) would, and returns
+ * XEB_EABORT; the message names stop.  A later call over [stop, end) gives
+ * the same amps as the two calls [begin, stop), [stop, end) without an abort.
+ * Errors: XEB_EINVAL (range), XEB_ESTATE (no workspace), XEB_EABORT, XEB_EHIP.
  */
 int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* amps,
                  void* stream);
@@ -401,12 +418,14 @@ int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_confi
  * amplitude buffer, the contraction of all its 2^s slices (as xeb_contract
  * over [0, 2^s)) and its XEB reduction, each plan on its own forked capture
  * stream (the plans share nothing), and instantiates the graph.  Every
- * xeb_batch_launch replays the whole batch with one hipGraphLaunch on
+ * xeb_batch_contract replays the whole batch with one hipGraphLaunch on
  * `stream`; afterwards each amplitude buffer holds its complete amplitudes
  * (a launch overwrites, it does not accumulate).
  *   plans (host) [n]: bound plans on one device, each listed once, n >= 1.
  *   amps (host) [n]: device complex128 [k_i] buffers, caller-owned; their
- *     addresses are captured, so they must stay valid while the batch lives.
+ *     addresses are captured in the graph (so they are passed here, not to
+ *     each replay), and they must stay valid while the batch lives.
+ * abort_after_slices does not apply to batch replays.
  * xeb_batch_fidelities waits for `stream` and writes each plan's F (host
  * double [n]; NaN for a plan with k = 0).
  * The plans must not be used by other calls while a launch is in flight;
@@ -422,7 +441,7 @@ int xeb_plan_set_node_config(xeb_plan_t plan, int32_t node, const xeb_node_confi
 #define XEB_BATCH_MAX_NODES 49152
 typedef struct xeb_batch* xeb_batch_t;
 int xeb_batch_create(const xeb_plan_t* plans, void* const* amps, int32_t n, xeb_batch_t* out);
-int xeb_batch_launch(xeb_batch_t batch, void* stream);
+int xeb_batch_contract(xeb_batch_t batch, void* stream);
 int xeb_batch_fidelities(xeb_batch_t batch, void* stream, double* F);
 int xeb_batch_destroy(xeb_batch_t batch);
 

@@ -2,6 +2,7 @@
 // across the boundary.
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -120,8 +121,19 @@ int xeb_plan_bind_workspace(xeb_plan_t plan, void* dev_ptr, uint64_t bytes) {
 int xeb_contract(xeb_plan_t plan, int64_t slice_begin, int64_t slice_end, void* amps,
                  void* stream) {
   return guarded([&] {
-    xeb::contract_plan(&impl(plan), slice_begin, slice_end, amps,
-                       static_cast<hipStream_t>(stream));
+    xeb::Plan& p = impl(plan);
+    // Injected abort: contract the slices left before the limit, then stop.
+    int64_t stop = slice_end;
+    if (p.opt.abort_after_slices > 0 && slice_begin >= 0 && slice_end >= slice_begin) {
+      const int64_t left = std::max<int64_t>(p.opt.abort_after_slices - p.slices_done, 0);
+      if (slice_end - slice_begin > left) stop = slice_begin + left;
+    }
+    xeb::contract_plan(&p, slice_begin, stop, amps, static_cast<hipStream_t>(stream));
+    p.slices_done += stop - slice_begin;
+    if (stop < slice_end)
+      xeb::fail(XEB_EABORT, "injected abort after " + std::to_string(p.slices_done) +
+                                " slices: [" + std::to_string(slice_begin) + ", " + std::to_string(stop) +
+                                ") are in amps; resume at slice " + std::to_string(stop));
   });
 }
 
@@ -178,6 +190,7 @@ int xeb_plan_stats(xeb_plan_t plan, xeb_stats_t* stats) {
   return guarded([&] {
     if (!stats) xeb::fail(XEB_EINVAL, "stats is NULL");
     *stats = impl(plan).stats;
+    stats->slices_done = impl(plan).slices_done;
   });
 }
 
@@ -259,7 +272,7 @@ int xeb_batch_create(const xeb_plan_t* plans, void* const* amps, int32_t n, xeb_
   });
 }
 
-int xeb_batch_launch(xeb_batch_t batch, void* stream) {
+int xeb_batch_contract(xeb_batch_t batch, void* stream) {
   return guarded([&] {
     if (!batch) xeb::fail(XEB_EINVAL, "batch handle is NULL");
     xeb::launch_batch(batch->impl, static_cast<hipStream_t>(stream));

@@ -263,6 +263,7 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
   if (o.max_ksplit < 0 || o.max_ksplit > 64 || (o.max_ksplit & (o.max_ksplit - 1)))
     fail(XEB_EINVAL, "max_ksplit must be 0 or a power of two up to 64");
   if (!(o.mfma_min_cmacs >= 0.0)) fail(XEB_EINVAL, "mfma_min_cmacs must be >= 0");
+  if (o.abort_after_slices < 0) fail(XEB_EINVAL, "abort_after_slices must be >= 0");
   p.opt = o;
 
   Net net = build_net(c, o.fuse_1q != 0, o.fold_kets != 0);

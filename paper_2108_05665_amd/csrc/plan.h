@@ -114,6 +114,7 @@ struct Plan {
   void* ws = nullptr;
   uint64_t ws_size = 0;
   xeb_stats_t stats{};
+  int64_t slices_done = 0;  // slices contracted by xeb_contract calls
   // Profiling (HIP events around launches).
   bool profiling = false;
   std::vector<ProfRecord> prof;  // records of the current profiling window

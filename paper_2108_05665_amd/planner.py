@@ -384,23 +384,43 @@ def choose_slicing(circ, bitstrings, memory_budget: int, max_sliced: int = 40, s
         best = {"children": ch, "sliced": sl, "stack_slices": 0, "workspace_bytes": need,
                 "n_blocks": int(st["n_blocks"]), "info": info, "tried": tried}
         if stack:
-            for J in range(len(sl), 0, -1):
-                if circ.n_qubits + J > 64:
-                    continue
-                try:
-                    p = _xeb.Plan(circ, bitstrings, ch, sl, fuse_1q=fuse_1q, fold_kets=fold_kets,
-                                  precision=precision, memory_budget=memory_budget,
-                                  stack_slices=J, bind=False)
-                except _xeb.XebError as e:
-                    if e.code != _xeb.XEB_ENOMEM:
-                        raise
-                    continue
-                st = p.stats()
-                p.close()
-                if int(st["n_blocks"]) > best["n_blocks"]:
-                    continue
+            J, st = choose_stacking(circ, bitstrings, ch, sl, memory_budget, precision=precision,
+                                    max_blocks=best["n_blocks"], fuse_1q=fuse_1q,
+                                    fold_kets=fold_kets)
+            if J > 0:
                 best.update(stack_slices=J, workspace_bytes=int(st["workspace_bytes"]),
                             n_blocks=int(st["n_blocks"]))
-                break
         return best
     raise ValueError(f"no slicing up to {max_sliced} legs fits {memory_budget} bytes")
+
+
+def choose_stacking(circ, bitstrings, children, sliced, memory_budget: int, precision: str = "c64",
+                    max_stack: int | None = None, max_blocks: int | None = None,
+                    fuse_1q: bool = True, fold_kets: bool = True):
+    """The largest number J of stacked slice bits (at most len(sliced), at
+    most max_stack, n_qubits + J <= 64) whose plan compiles within
+    `memory_budget` with at most `max_blocks` string blocks (default: the
+    unstacked plan's count), by the plan compiler's host dry run.  Returns
+    (J, the plan's stats); (0, None) when no J > 0 qualifies."""
+    if max_blocks is None:
+        p = _xeb.Plan(circ, bitstrings, children, sliced, fuse_1q=fuse_1q, fold_kets=fold_kets,
+                      precision=precision, memory_budget=memory_budget, bind=False)
+        max_blocks = int(p.stats()["n_blocks"])
+        p.close()
+    top = len(sliced) if max_stack is None else min(len(sliced), max_stack)
+    for J in range(top, 0, -1):
+        if circ.n_qubits + J > 64:
+            continue
+        try:
+            p = _xeb.Plan(circ, bitstrings, children, sliced, fuse_1q=fuse_1q, fold_kets=fold_kets,
+                          precision=precision, memory_budget=memory_budget, stack_slices=J,
+                          bind=False)
+        except _xeb.XebError as e:
+            if e.code != _xeb.XEB_ENOMEM:
+                raise
+            continue
+        st = p.stats()
+        p.close()
+        if int(st["n_blocks"]) <= max_blocks:
+            return J, st
+    return 0, None

@@ -22,6 +22,7 @@ XEB_ENOMEM = -2
 XEB_EHIP = -3
 XEB_ESTATE = -4
 XEB_ELIMIT = -5
+XEB_EABORT = -6
 BATCH_MAX_NODES = 49152  # nodes of one batch graph (XEB_BATCH_MAX_NODES)
 
 PRECISIONS = {"c64": 0, "split_fp16": 1, "split_bf16": 2}
@@ -72,6 +73,7 @@ class Options(ctypes.Structure):
         ("mfma_min_cmacs", ctypes.c_double),
         ("stack_slices", ctypes.c_int32),
         ("open_qubits", ctypes.c_uint64),
+        ("abort_after_slices", ctypes.c_int64),
     ]
 
 
@@ -93,6 +95,7 @@ class Stats(ctypes.Structure):
         ("n_blocks", ctypes.c_int64),
         ("n_stacked", ctypes.c_int32),
         ("n_open", ctypes.c_int32),
+        ("slices_done", ctypes.c_int64),
     ]
 
 
@@ -177,7 +180,7 @@ _SIG = {
     "xeb_plan_read_node_profile": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(KernelProfile)]),
     "xeb_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int32,
                                         ctypes.POINTER(_P)]),
-    "xeb_batch_launch": (ctypes.c_int, [_P, _P]),
+    "xeb_batch_contract": (ctypes.c_int, [_P, _P]),
     "xeb_batch_fidelities": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "xeb_batch_destroy": (ctypes.c_int, [_P]),
     "xeb_plan_destroy": (ctypes.c_int, [_P]),
@@ -254,7 +257,7 @@ class Plan:
     def __init__(self, circ, bitstrings, tree_children, sliced_legs=(), *, fuse_1q=True,
                  fold_kets=True, precision="c64", device=None, memory_budget=0, trace=0,
                  force_generic=False, max_ksplit=0, mfma_min_cmacs=0.0, stack_slices=0,
-                 open_qubits=0, bind=True):
+                 open_qubits=0, abort_after_slices=0, bind=True):
         self._h = _P()
         c, keep = _circuit_struct(circ)
         bs = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
@@ -275,6 +278,7 @@ class Plan:
         o.mfma_min_cmacs = float(mfma_min_cmacs)
         o.stack_slices = int(stack_slices)
         o.open_qubits = int(open_qubits)
+        o.abort_after_slices = int(abort_after_slices)
         _check(_lib.xeb_plan_create(ctypes.byref(c), bs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                     bs.size, ctypes.byref(tree),
                                     sl.ctypes.data_as(_I32P) if sl.size else None, sl.size,
@@ -328,8 +332,8 @@ class Plan:
             slice_end = self.n_slices
         import torch
 
-        if amps.dtype != torch.complex128 or not amps.is_cuda or amps.numel() < self.k:
-            raise ValueError("amps must be a CUDA complex128 tensor with k elements")
+        if amps.dtype != torch.complex128 or not amps.is_cuda or amps.numel() < (self.k << self.n_open):
+            raise ValueError("amps must be a CUDA complex128 tensor with k * 2^w elements")
         if not amps.is_contiguous():
             raise ValueError("amps must be contiguous")
         _check(_lib.xeb_contract(self._h, int(slice_begin), int(slice_end),
@@ -420,7 +424,7 @@ class Batch:
         _check(_lib.xeb_batch_create(ph, ah, len(self.plans), ctypes.byref(self._h)))
 
     def launch(self, stream=None):
-        _check(_lib.xeb_batch_launch(self._h, Plan._stream_handle(stream)))
+        _check(_lib.xeb_batch_contract(self._h, Plan._stream_handle(stream)))
 
     def fidelities(self, stream=None):
         out = (ctypes.c_double * len(self.plans))()

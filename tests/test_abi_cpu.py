@@ -456,3 +456,36 @@ def test_open_qubits_counts_and_root(open_q):
         assert root["m_bits"] + root["n_bits"] == w
     with pytest.raises(xeb.XebError):
         xeb.Plan(c, s, ch, sl, open_qubits=1 << 12, bind=False)
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """Every struct of the binding has the size and field offsets that the C
+    compiler gives the header's declaration (compiled here with gcc)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = {"xeb_circuit_t": xeb.Circuit, "xeb_tree_t": xeb.Tree, "xeb_options_t": xeb.Options,
+             "xeb_stats_t": xeb.Stats, "xeb_node_stats_t": xeb.NodeStats,
+             "xeb_kernel_profile_t": xeb.KernelProfile, "xeb_autotune_report_t": xeb.AutotuneReport,
+             "xeb_node_config_t": xeb.NodeConfig}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "xeb.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for cname, cls in pairs.items():
+        want.append(f"{cname} size {ctypes.sizeof(cls)}")
+        for fname, _ in cls._fields_:
+            want.append(f"{cname} {fname} {getattr(cls, fname).offset}")
+    assert [g for g in got if g] == want
