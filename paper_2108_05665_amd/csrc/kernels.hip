@@ -1285,15 +1285,21 @@ __global__ void __launch_bounds__(256) k_presplit(const float2* src, int64_t row
 // workgroups per CU), tile 7 WMT = 4 (256 x 128, eight waves).  K slabs of
 // 16 complex go from global memory straight into LDS (global_load_lds, 16
 // bytes per lane: each load instruction of a wave fills 1 KB of LDS, eight
-// rows of 128 bytes) through a ring of NBUF buffers: while the MFMAs consume
-// slab j, the loads of slabs j + 1 .. j + NBUF - 1 are in flight, with one
-// barrier per slab.  Inside a 128-byte row the eight 16-byte chunks (hi re,
+// rows of 128 bytes) through two buffers: while the MFMAs consume slab j,
+// the loads of slab j + 1 are in flight, with one barrier per slab.  (A
+// third buffer for tile 7, loads two slabs ahead, measured 5-7 % slower.)  Inside a 128-byte row the eight 16-byte chunks (hi re,
 // hi im, lo re, lo im; two each) sit at chunk position c ^ (row & 7), so
 // that the fragment reads of eight consecutive rows hit distinct banks.
 // The epilogue writes 64-row slices of the tile through LDS.  Needs K >= 16
 // and no split K.
+// s_waitcnt immediate (gfx9 layout: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8) that waits for every vector memory load of the wave and
+// for nothing else.
+constexpr int kWaitVmcnt0 = (7 << 4) | (15 << 8);
+
 template <int PREC, int WMT, int NBUF>
 __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes(ContractArgs g) {
+  static_assert(NBUF == 2, "two LDS buffers: slab j + 1 loads while slab j multiplies");
   constexpr int BM = 64 * WMT, BN = 128, TK = kPlaneTK;
   constexpr int NT = 128 * WMT, NW = 2 * WMT;    // threads, waves
   constexpr int ROW_B = 8 * TK;                  // bytes of one row slab (128)
@@ -1367,20 +1373,30 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
                                        (__attribute__((address_space(3))) void*)(dst + A_B + 1024 * blk), 16, 0, 0);
     }
   };
-  // Fragment (row r, chunk c) of an operand slab at `base`.
-  auto frag = [&](const char* base, int r, int c) -> u32x4 {
-    return *reinterpret_cast<const u32x4*>(base + r * ROW_B + 16 * (c ^ (r & 7)));
+  // The 16 fragments of one slab: ar[fm][pl] = A row 64 wm + 32 fm + (lane %
+  // 32), chunk 2 pl + lane / 32; br[fn][pl] the same for B row 64 wn + 32 fn
+  // + (lane % 32).  Chunk c of row r sits at byte 16 (c ^ (r % 8)) of the
+  // row, and r % 8 = lane % 8 for every fragment.
+  const int li = lane & 31, lg = lane >> 5;
+  int offA[4], offB[4];
+#pragma unroll
+  for (int pl = 0; pl < 4; ++pl) {
+    const int chunk = 16 * ((2 * pl + lg) ^ (li & 7));
+    offA[pl] = (wm * 64 + li) * ROW_B + chunk;
+    offB[pl] = A_B + (wn * 64 + li) * ROW_B + chunk;
+  }
+  auto read_frags = [&](const char* buf, u32x4 (&ar)[2][4], u32x4 (&br)[2][4]) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        ar[f][pl] = *reinterpret_cast<const u32x4*>(buf + offA[pl] + f * 32 * ROW_B);
+        br[f][pl] = *reinterpret_cast<const u32x4*>(buf + offB[pl] + f * 32 * ROW_B);
+      }
   };
-  // s_waitcnt: this wave's loads of all but the last n slabs issued have
-  // landed (vmcnt = n (LA + LB); expcnt and lgkmcnt not waited on).
-  constexpr int LPS = LA + LB;
-  constexpr int WAIT_KEEP = (NBUF - 2) * LPS;
-  static_assert(WAIT_KEEP < 64, "vmcnt field");
-  constexpr int WAIT_IMM = (WAIT_KEEP & 15) | ((WAIT_KEEP >> 4) << 14) | (7 << 4) | (15 << 8);
 
   int64_t p = blockIdx.x;
   if (p < walk && item_of(p) >= tiles) p = next_p(p);
-  const int li = lane & 31, lg = lane >> 5;
   while (p < walk) {
     const TileOrigin o = tmap.at(g, item_of(p));
     const int64_t pn = next_p(p);
@@ -1392,29 +1408,25 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc_re[fm][fn][v] = acc_im[fm][fn][v] = 0.f;
 
-#pragma unroll
-    for (int q = 0; q < NBUF - 1; ++q)
-      if (q < nslabs) issue(o, q, q);
+    // Per slab j: wait for this wave's loads of slab j, barrier (slab j is in
+    // LDS everywhere, and nobody reads slab j - 1's buffer any more), all
+    // fragments of slab j into registers, the loads of slab j + 1 into the
+    // other buffer, then the MFMAs.  The compiler makes an LDS read wait for
+    // every LDS-bound load in flight (it cannot tell the buffers apart), so
+    // the reads come before the next slab's loads are issued; those then
+    // overlap the MFMAs.
+    issue(o, 0, 0);
     for (int j = 0; j < nslabs; ++j) {
-      // This wave's loads of slab j have landed (later slabs may be in flight).
-      if (j + NBUF - 2 < nslabs)
-        __builtin_amdgcn_s_waitcnt(WAIT_IMM);
-      else
-        __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();  // everyone's have; slab j - 1's buffer is free
-      if (j + NBUF - 1 < nslabs) issue(o, j + NBUF - 1, (j + NBUF - 1) % NBUF);
-      const char* bufA = lds + (j % NBUF) * BUF_B;
-      const char* bufB = bufA + A_B;
-      u32x4 ar[2][4];
-#pragma unroll
-      for (int fm = 0; fm < 2; ++fm)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) ar[fm][pl] = frag(bufA, wm * 64 + fm * 32 + li, 2 * pl + lg);
+      // The barrier's fence does not wait for loads: wait for this wave's
+      // loads of slab j explicitly before it.
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __syncthreads();
+      u32x4 ar[2][4], br[2][4];
+      read_frags(lds + (j & 1) * BUF_B, ar, br);
+      if (j + 1 < nslabs) issue(o, j + 1, (j + 1) & 1);
 #pragma unroll
       for (int fn = 0; fn < 2; ++fn) {
-        const int rb = wn * 64 + fn * 32 + li;
-        const u32x4 brh = frag(bufB, rb, lg), bih = frag(bufB, rb, 2 + lg);
-        const u32x4 brl = frag(bufB, rb, 4 + lg), bil = frag(bufB, rb, 6 + lg);
+        const u32x4 brh = br[fn][0], bih = br[fn][1], brl = br[fn][2], bil = br[fn][3];
         const u32x4 nbih = bih ^ 0x80008000u, nbil = bil ^ 0x80008000u;
 #pragma unroll
         for (int fm = 0; fm < 2; ++fm) {
@@ -1637,7 +1649,7 @@ unsigned persistent_grid(int64_t tiles) {
     else if constexpr (CFG == 6)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC, 2, 2>, 256, 0);
     else if constexpr (CFG == 8)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC, 4, 3>, 512, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_planes<PREC, 4, 2>, 512, 0);
     else
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract_split<CFG, PREC, TKV, KG>, 256 * KG, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
@@ -1681,7 +1693,7 @@ void launch_cfg(const ContractArgs& a, hipStream_t s, int64_t rowsA, int64_t row
       launch(k_contract_planes<PREC, 2, 2>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(256), s,
              false, true, a);
     else
-      launch(k_contract_planes<PREC, 4, 3>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(512), s,
+      launch(k_contract_planes<PREC, 4, 2>, dim3(persistent_grid<CFG, PREC, TKV, KG>(tiles)), dim3(512), s,
              false, true, a);
   }
   else
