@@ -495,6 +495,17 @@ __device__ __forceinline__ void epilogue_setup(const ContractArgs& g, int64_t* d
 // Writes a finished tile parked in LDS (Ct, rows of BN + 1) to the output
 // table in the write order ubit (NT threads); returns the largest |re|, |im|
 // written.
+//
+// An element's output offset is a sum over the set bits of its row and
+// column index inside the tile: a row bit below mb deposits to its output
+// position, a row bit at or above mb steps the row operand's variant (dense
+// keys: a fixed stride of keys; keyed form: out of the key's rows, masked by
+// the bounds); columns alike.  So the offsets of one thread's elements follow
+// from its first one by adding one per-bit delta per element, walking the
+// element numbers in Gray-code order (one bit changes per step).  The table
+// form (pair_mode 1) looks its key up per (row variant, column variant); the
+// walk applies when the tile spans one of each, otherwise every element
+// looks its key up.
 template <int CFG, int NT = 256>
 __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const float2* Ct,
                                                 int64_t row0, int64_t col0, int64_t key,
@@ -505,11 +516,83 @@ __device__ __forceinline__ float epilogue_write(const ContractArgs& g, const flo
   constexpr int BM = T::BM, BN = T::BN;
   constexpr int LOG_NT = NT == 512 ? 9 : 8;
   constexpr int PER_THREAD = BM * BN / NT;
+  constexpr int UB = T::UBITS - LOG_NT;  // element-number bits walked per thread
   const int64_t M = int64_t(1) << g.mb, N = int64_t(1) << g.nb;
   const int64_t sizeC = M * N;
   const int64_t dep_m_hi = M > BM ? deposit(row0 & (M - 1), g.mapM) : 0;
   const int64_t dep_n_hi = N > BN ? deposit(col0 & (N - 1), g.mapN) : 0;
   float amax = 0.f;
+  if (g.pair_mode != 1 || (M >= BM && N >= BN)) {
+    int64_t a0 = key;
+    if (key < 0) {
+      const int64_t rv = row0 >> g.mb, cv = col0 >> g.nb;
+      a0 = g.swapped ? cv * g.nvarA + rv : rv * g.nvarB + cv;
+      if (g.pair_mode == 1) a0 = g.pairs[a0];
+      if (a0 < 0) return 0.f;
+    }
+    // Offset steps of one more row / column variant (dense keys only; in the
+    // keyed form such rows and columns lie outside the bounds).
+    const int64_t key_r = g.pair_mode == 0 ? (g.swapped ? 1 : g.nvarB) * sizeC : 0;
+    const int64_t key_c = g.pair_mode == 0 ? (g.swapped ? g.nvarA : 1) * sizeC : 0;
+    float2* out = g.C + a0 * sizeC + dep_m_hi + dep_n_hi + dep_m_lo[r_tid & (BM - 1)] +
+                  dep_n_lo[c_tid & (BN - 1)] + (int64_t(r_tid) >> g.mb) * key_r +
+                  (int64_t(c_tid) >> g.nb) * key_c;
+    int lds = r_tid * (BN + 1) + c_tid;
+    // Per element-number bit: offset, LDS and row / column steps.  All are
+    // uniform (kernel arguments only), so they stay in scalar registers.
+    int64_t dg[UB > 0 ? UB : 1];
+    int dl[UB > 0 ? UB : 1], dr[UB > 0 ? UB : 1], dc[UB > 0 ? UB : 1];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) {
+      const int u = g.ubit[LOG_NT + k];
+      if (u < 32) {
+        dg[k] = (int64_t(1) << u) < M ? deposit(uint64_t(1) << u, g.mapM)
+                                      : (int64_t(1) << (u - g.mb)) * key_r;
+        dl[k] = (1 << u) * (BN + 1);
+        dr[k] = 1 << u;
+        dc[k] = 0;
+      } else {
+        dg[k] = (int64_t(1) << (u - 32)) < N ? deposit(uint64_t(1) << (u - 32), g.mapN)
+                                             : (int64_t(1) << (u - 32 - g.nb)) * key_c;
+        dl[k] = 1 << (u - 32);
+        dr[k] = 0;
+        dc[k] = 1 << (u - 32);
+      }
+    }
+    if (row0 + BM <= row_end && col0 + BN <= col_end) {
+#pragma unroll
+      for (int s = 0; s < PER_THREAD; ++s) {
+        if (s > 0) {
+          const int k = __builtin_ctz(s);
+          const bool up = ((s ^ (s >> 1)) >> k) & 1;
+          out += up ? dg[k] : -dg[k];
+          lds += up ? dl[k] : -dl[k];
+        }
+        const float2 val = Ct[lds];
+        *out = val;
+        amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
+      }
+    } else {
+      int r = r_tid, c = c_tid;
+#pragma unroll
+      for (int s = 0; s < PER_THREAD; ++s) {
+        if (s > 0) {
+          const int k = __builtin_ctz(s);
+          const bool up = ((s ^ (s >> 1)) >> k) & 1;
+          out += up ? dg[k] : -dg[k];
+          lds += up ? dl[k] : -dl[k];
+          r ^= dr[k];
+          c ^= dc[k];
+        }
+        if (row0 + r < row_end && col0 + c < col_end) {
+          const float2 val = Ct[lds];
+          *out = val;
+          amax = fmaxf(amax, fmaxf(fabsf(val.x), fabsf(val.y)));
+        }
+      }
+    }
+    return amax;
+  }
 #pragma unroll 4
   for (int t = 0; t < PER_THREAD; ++t) {
     int r = r_tid, c = c_tid;
