@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
 //      k_contract_split_db)
 //   6: 128 x 128, four waves of 64 x 64 on operands converted once into
 //      hi/lo planes (split forms only, k_presplit + k_contract_planes)
-//   7: 256 x 128, eight waves of 64 x 64 on plane-format operands, a ring
-//      of three LDS buffers (split forms only)
+//   7: 256 x 128, eight waves of 64 x 64 on plane-format operands (split
+//      forms only)
 // Precisions:
 //   PREC 0 (complex64): v_mfma_f32_32x32x2f32 / 16x16x4f32; a complex k costs
 //     4 real MACs: the instruction's K runs over (re, im) of the row operand
@@ -1379,9 +1379,12 @@ __global__ void __launch_bounds__(256) k_presplit(const float2* src, int64_t row
 // lgkmcnt 11:8) that waits for every vector memory load of the wave and
 // for nothing else.
 constexpr int kWaitVmcnt0 = (7 << 4) | (15 << 8);
+// Word 3 of a raw buffer resource (no format conversion, no swizzle).
+constexpr int kBufferFlags = 0x00020000;
 
 template <int PREC, int WMT, int NBUF>
 __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes(ContractArgs g) {
+#if defined(__HIP_DEVICE_COMPILE__)  // buffer resources exist on the device side only
   static_assert(NBUF == 2, "two LDS buffers: slab j + 1 loads while slab j multiplies");
   constexpr int BM = 64 * WMT, BN = 128, TK = kPlaneTK;
   constexpr int NT = 128 * WMT, NW = 2 * WMT;    // threads, waves
@@ -1436,25 +1439,41 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
   // Lane l of the wave's load into 1 KB block b fills its bytes 16 l: row
   // 8 b + l / 8, position l % 8, i.e. chunk (l % 8) ^ (row % 8) of the row.
   const int lrow = lane >> 3, lpos = lane & 7;
-  auto issue = [&](const TileOrigin& o, int j, int buf) {
+  // Loads as buffer loads into LDS: per tile one buffer resource per operand
+  // (base = the tile's first row; its rows fit 2^31 bytes, K <= 2^18), a
+  // 32-bit offset per lane and load fixed for the tile (rows past the end
+  // clamp to the last row), and the slab offset as the scalar offset.
+  uint32_t offLA[LA], offLB[LB];
+  __amdgpu_buffer_rsrc_t rsA, rsB;
+  auto tile_rows = [&](const TileOrigin& o) {
     const int64_t la = o.row_end - o.row0 - 1, lb = o.col_end - o.col0 - 1;
-    const char* baseA = Ap + uint64_t(o.row0) * row_bytes + uint64_t(j) * ROW_B;
-    const char* baseB = Bp + uint64_t(o.col0) * row_bytes + uint64_t(j) * ROW_B;
-    char* dst = lds + buf * BUF_B;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int blk = NW * i + wave, r = 8 * blk + lrow;
-      const int64_t ra = r < la ? r : la;
-      __builtin_amdgcn_global_load_lds(baseA + uint64_t(ra) * row_bytes + 16 * (lpos ^ (r & 7)),
-                                       (__attribute__((address_space(3))) void*)(dst + 1024 * blk), 16, 0, 0);
+      offLA[i] = uint32_t(r < la ? r : la) * uint32_t(row_bytes) + 16u * uint32_t(lpos ^ (r & 7));
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int blk = NW * i + wave, r = 8 * blk + lrow;
-      const int64_t rb = r < lb ? r : lb;
-      __builtin_amdgcn_global_load_lds(baseB + uint64_t(rb) * row_bytes + 16 * (lpos ^ (r & 7)),
-                                       (__attribute__((address_space(3))) void*)(dst + A_B + 1024 * blk), 16, 0, 0);
+      offLB[i] = uint32_t(r < lb ? r : lb) * uint32_t(row_bytes) + 16u * uint32_t(lpos ^ (r & 7));
     }
+    rsA = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(Ap + uint64_t(o.row0) * row_bytes), 0,
+                                            int(uint32_t(BM) * uint32_t(row_bytes)), kBufferFlags);
+    rsB = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(Bp + uint64_t(o.col0) * row_bytes), 0,
+                                            int(uint32_t(BN) * uint32_t(row_bytes)), kBufferFlags);
+  };
+  auto issue = [&](int j, int buf) {
+    char* dst = lds + buf * BUF_B;
+#pragma unroll
+    for (int i = 0; i < LA; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsA, (__attribute__((address_space(3))) void*)(dst + 1024 * (NW * i + wave)), 16, offLA[i],
+          j * ROW_B, 0, 0);
+#pragma unroll
+    for (int i = 0; i < LB; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsB, (__attribute__((address_space(3))) void*)(dst + A_B + 1024 * (NW * i + wave)), 16, offLB[i],
+          j * ROW_B, 0, 0);
   };
   // The 16 fragments of one slab: ar[fm][pl] = A row 64 wm + 32 fm + (lane %
   // 32), chunk 2 pl + lane / 32; br[fn][pl] the same for B row 64 wn + 32 fn
@@ -1498,7 +1517,8 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
     // every LDS-bound load in flight (it cannot tell the buffers apart), so
     // the reads come before the next slab's loads are issued; those then
     // overlap the MFMAs.
-    issue(o, 0, 0);
+    tile_rows(o);
+    issue(0, 0);
     for (int j = 0; j < nslabs; ++j) {
       // The barrier's fence does not wait for loads: wait for this wave's
       // loads of slab j explicitly before it.
@@ -1506,7 +1526,7 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
       __syncthreads();
       u32x4 ar[2][4], br[2][4];
       read_frags(lds + (j & 1) * BUF_B, ar, br);
-      if (j + 1 < nslabs) issue(o, j + 1, (j + 1) & 1);
+      if (j + 1 < nslabs) issue(j + 1, (j + 1) & 1);
 #pragma unroll
       for (int fn = 0; fn < 2; ++fn) {
         const u32x4 brh = br[fn][0], bih = br[fn][1], brl = br[fn][2], bil = br[fn][3];
@@ -1557,6 +1577,7 @@ __global__ void __launch_bounds__(128 * WMT, WMT == 2 ? 2 : 1) k_contract_planes
     p = pn;
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+#endif
 }
 
 // Split-K chunk sum: partial[0] += partial[1] + ... + partial[ksplit - 1],

@@ -138,7 +138,7 @@ uint64_t planes_need(const Node& nd, int64_t nvarL, int64_t nvarR) {
 
 bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock& nb, int tile,
                   int swapped, int ksplit, int keyed) {
-  if ((tile == 6 || tile == 7) && (nd.kb < 4 || ksplit != 1)) return false;
+  if ((tile == 6 || tile == 7) && (nd.kb < 4 || nd.kb > 18 || ksplit != 1)) return false;
   const bool stacked = mfma_capable(nd, nvarL, nvarR, nb);
   if (stacked && !keyed) return true;
   return ksplit == 1 && nd.kb >= 1 && nd.kb <= 21 && mfma_keyed_fits(nd, tile, swapped) &&

@@ -54,3 +54,53 @@ def test_share53_slice_partials_vs_oracle(precision):
         del a
     p.close()
     torch.cuda.empty_cache()
+
+
+SINGLE = os.path.join(ROOT, "tests", "data", "share_53q_m14_single_plan.json")
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "c64"])
+def test_share53_single_tree_amplitudes_match_sliced_contraction(precision):
+    """The single-amplitude tree at full size (53 qubits, 14 cycles, no
+    slicing, strings in blocks under 270 GiB): complete amplitudes of the
+    first 16 strings equal the same tree's contraction with 4 sliced legs
+    summed over its 16 slices (Appendix A, "Slicing": the sum over a sliced
+    leg's values restores the contraction).  No FP64 value exists at this
+    size; the two contractions share no partial tensor and each carries its
+    own FP32 rounding, so their difference is bounded by twice the
+    precision's bound against the exact amplitudes (at this depth the
+    sliced fixture's partials sit near 1e-5 of the oracle's in both forms)."""
+    from paper_2108_05665_amd import planner
+
+    with open(SINGLE) as f:
+        fx = json.load(f)
+    assert fx["sliced"] == [] and fx["info"]["max_log2"] <= 30
+    circ = config_circuit("share_53q_m14")
+    strings = config_bitstrings("share_53q_m14", circ.n_qubits)[:16]
+    torch.cuda.empty_cache()
+    p = xeb.Plan(circ, strings, fx["children"], [], precision=precision, memory_budget=270 * 2**30)
+    assert p.stats()["n_blocks"] >= 2
+    a = p.new_amps()
+    p.contract(a)
+    torch.cuda.synchronize()
+    full = a.cpu().numpy()
+    p.close()
+    del a
+    torch.cuda.empty_cache()
+    st = planner.Structure(circ)
+    cnt = planner.VariantCounter(strings)
+    ch = [tuple(x) for x in fx["children"]]
+    sl = planner.order_slices(st, ch, cnt, planner.greedy_slices(st, ch, cnt, 4))
+    assert len(sl) == 4
+    p2 = xeb.Plan(circ, strings, fx["children"], sl, precision=precision, memory_budget=270 * 2**30)
+    b = p2.new_amps()
+    p2.contract(b)
+    torch.cuda.synchronize()
+    sliced = b.cpu().numpy()
+    p2.close()
+    del b
+    torch.cuda.empty_cache()
+    assert np.all(np.isfinite(full)) and np.linalg.norm(sliced) > 0
+    rel = float(np.linalg.norm(full - sliced) / np.linalg.norm(sliced))
+    print(f"{precision}: single tree vs 16-slice contraction {rel:.2e}")
+    assert rel <= 2 * TOL[precision], rel
