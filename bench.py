@@ -216,6 +216,10 @@ def main() -> int:
     ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "batch32", "share53"],
                     help="the 36-qubit workload (default), the 32-circuit batch, or one GPU's "
                          "share of the 53-qubit contraction (a block of slices)")
+    ap.add_argument("--share53-tree", default="single", choices=["single", "sliced"],
+                    help="share53: the single-amplitude tree without slicing, or the sliced fixture")
+    ap.add_argument("--share53-strings", type=int, default=1024,
+                    help="share53 single: strings contracted (the first ones)")
     ap.add_argument("--slice-block", type=int, default=256,
                     help="share53: slices contracted (a contiguous block from slice 0)")
     ap.add_argument("--batch-budget-gib", type=float, default=None,
@@ -666,19 +670,31 @@ def batch_main(args) -> int:
 
 SHARE53 = "share_53q_m14"
 SHARE53_PLAN = os.path.join(ROOT, "tests", "data", f"{SHARE53}_plan.json")
+SHARE53_SINGLE_PLAN = os.path.join(ROOT, "tests", "data", f"{SHARE53}_single_plan.json")
 SHARE53_GOLDEN = os.path.join(ROOT, "tests", "golden", f"{SHARE53}_partials.json")
 SHARE53_BUDGET = 270 * 2**30
 
 
 def share53_main(args) -> int:
     """One GPU's share of the 53-qubit contraction (6x9 grid minus site
-    (0, 4), 14 cycles, 3 * 10^5 uniform strings): the plan fixture's tree and
-    sliced legs, compiled within 270 GiB of HBM; a contiguous block of slices
-    [0, --slice-block) contracted with the memo tables in split FP16 (and
-    the other --precisions).  Reports the time per slice and the full
-    contraction extrapolated as t_block * 2^s / block, and checks single-slice
-    partials of the first strings against the stored FP64 oracle values
-    (no amplitude or XEB: a partial block yields neither)."""
+    (0, 4), 14 cycles, 3 * 10^5 uniform strings), in one of two plans:
+
+    * "single" (default): the tree annealed for one amplitude (the paper's
+      objective, largest tensor 2^28), no sliced legs: with 270 GiB of HBM the
+      plan compiler cuts the strings into blocks of 32.  The first
+      --share53-strings strings are contracted completely and timed; the full
+      share is extrapolated as 3 * 10^5 strings at that rate (each string's
+      work is the same: the uniform strings share only the smallest
+      subtrees).  The amplitudes of those strings give their XEB and the
+      Porter-Thomas mean of 2^n |amp|^2 (both near 0 and 1 for uniform
+      strings), and the first 8 are checked against the same tree with 4
+      sliced legs summed over its 16 slices.
+    * "sliced": the fixture's tree and 2^25 slices compiled within 270 GiB;
+      a contiguous block of slices [0, --slice-block) contracted with the memo
+      tables; the time per slice and the full contraction extrapolated as
+      t_block * 2^s / block, with single-slice partials of the first strings
+      checked against the stored FP64 oracle values (a partial block yields
+      no amplitude)."""
     import numpy as np
 
     from synth import config_circuit, config_bitstrings
@@ -686,22 +702,33 @@ def share53_main(args) -> int:
 
     circ = config_circuit(SHARE53)
     strings = config_bitstrings(SHARE53, circ.n_qubits)
+    single = args.share53_tree == "single"
     if args.plan_only:
         t0 = time.perf_counter()
-        ch, sl, info = planner.plan(circ, strings, n_sliced=20, trials=8, seed=0, anneal_steps=200000,
-                                    anneal_restarts=4, workers=4, anneal_objective="paper",
-                                    table_bytes_max=250 * 2**30, memory="tables", slicing="paper",
-                                    slice_every=5000, size_log2_max=34)
+        if single:
+            ch, sl, info = planner.plan(circ, strings[:1], n_sliced=0, trials=16, seed=1,
+                                        anneal_steps=10_000_000, anneal_restarts=8, workers=8,
+                                        anneal_objective="paper", size_log2_max=28)
+        else:
+            ch, sl, info = planner.plan(circ, strings, n_sliced=20, trials=8, seed=0,
+                                        anneal_steps=200000, anneal_restarts=4, workers=4,
+                                        anneal_objective="paper", table_bytes_max=250 * 2**30,
+                                        memory="tables", slicing="paper", slice_every=5000,
+                                        size_log2_max=34)
         with open(args.plan_only, "w") as f:
             json.dump({"workload": SHARE53, "children": [[int(a), int(b)] for a, b in ch],
-                       "sliced": [int(x) for x in sl], "info": info}, f)
+                       "sliced": [int(x) for x in sl], "info": info,
+                       "made_by": f"python bench.py --workload share53 --share53-tree "
+                                  f"{args.share53_tree} --plan-only PATH"}, f)
         log(f"planned in {time.perf_counter() - t0:.0f} s: cost {info['cost']:.3e}, s = {len(sl)}")
         return 0
     import torch
 
+    precs = [p.strip() for p in (args.precisions or "split_fp16").split(",") if p.strip()]
+    if single:
+        return share53_single(args, circ, strings, precs)
     with open(SHARE53_PLAN) as f:
         fx = json.load(f)
-    precs = [p.strip() for p in (args.precisions or "split_fp16").split(",") if p.strip()]
     n_slices = 1 << len(fx["sliced"])
     block = min(args.slice_block, n_slices)
     gold = None
@@ -755,6 +782,78 @@ def share53_main(args) -> int:
         "config": {"workload": f"{SHARE53}: 53 qubits (6x9 grid minus (0, 4)), 14 cycles, 3*10^5 "
                                f"uniform strings, 2^{len(fx['sliced'])} slices, block of {block}",
                    "slices": n_slices, "block": block},
+        "forms": results, "plan": fx["info"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def share53_single(args, circ, strings, precs) -> int:
+    import numpy as np
+    import torch
+
+    from paper_2108_05665_amd import planner, xeb
+
+    with open(SHARE53_SINGLE_PLAN) as f:
+        fx = json.load(f)
+    k = min(args.share53_strings, len(strings))
+    sub = strings[:k]
+    results = {}
+    for prec in precs:
+        t0 = time.perf_counter()
+        plan = xeb.Plan(circ, sub, fx["children"], [], precision=prec, memory_budget=SHARE53_BUDGET)
+        st = plan.stats()
+        t_plan = time.perf_counter() - t0
+        log(f"{prec}: plan for {k} strings compiled and bound in {t_plan:.1f} s, workspace "
+            f"{st['workspace_bytes'] / 2**30:.1f} GiB, {st['n_blocks']} string blocks, "
+            f"{st['cmacs_full']:.3e} complex MACs")
+        amps = plan.new_amps()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.contract(amps)
+        F = plan.fidelity(amps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        a = amps.cpu().numpy()
+        pt = float(np.mean(np.ldexp(np.abs(a) ** 2, circ.n_qubits)))
+        log(f"{prec}: {k} strings in {sec:.1f} s ({k / sec:.1f} amplitudes/s), XEB {F:.4f}, "
+            f"mean 2^n|amp|^2 {pt:.4f}")
+        plan.close()
+        del amps
+        torch.cuda.empty_cache()
+        # The same tree with 4 sliced legs: 16 slices summed for the first 8 strings.
+        st_ = planner.Structure(circ)
+        cnt = planner.VariantCounter(sub[:8])
+        ch = [tuple(x) for x in fx["children"]]
+        sl = planner.order_slices(st_, ch, cnt, planner.greedy_slices(st_, ch, cnt, 4))
+        p2 = xeb.Plan(circ, sub[:8], fx["children"], sl, precision=prec, memory_budget=SHARE53_BUDGET)
+        b = p2.new_amps()
+        p2.contract(b)
+        torch.cuda.synchronize()
+        sliced = b.cpu().numpy()
+        p2.close()
+        del b
+        torch.cuda.empty_cache()
+        diff = float(np.linalg.norm(a[:8] - sliced) / np.linalg.norm(sliced))
+        log(f"{prec}: first 8 strings vs the 16-slice contraction: {diff:.2e}")
+        results[prec] = {"strings": k, "seconds": sec, "amplitudes_per_s": k / sec,
+                         "extrapolated_full_s": len(strings) * sec / k,
+                         "cmacs": st["cmacs_full"],
+                         "algorithmic_tflops": 8 * st["cmacs_full"] / sec / 1e12,
+                         "n_blocks": st["n_blocks"], "workspace_gib": st["workspace_bytes"] / 2**30,
+                         "plan_s": t_plan, "xeb": F, "porter_thomas_mean": pt,
+                         "sliced_check": {"strings": 8, "sliced_legs": len(sl), "rel_diff": diff}}
+    head = results[precs[0]]
+    out = {
+        "metric": "amplitudes/sec (53-qubit share, full contraction of a string sample, "
+                  "extrapolated to all strings)",
+        "value": head["amplitudes_per_s"], "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 * head["seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[precs[0]], "data": "synthetic",
+        "config": {"workload": f"{SHARE53}: 53 qubits (6x9 grid minus (0, 4)), 14 cycles, 3*10^5 "
+                               f"uniform strings; single-amplitude tree, no slicing, strings in "
+                               f"blocks under 270 GiB; the first {k} strings contracted",
+                   "strings_total": len(strings), "strings_run": k},
         "forms": results, "plan": fx["info"],
     }
     print(json.dumps(out), flush=True)

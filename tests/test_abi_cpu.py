@@ -489,3 +489,26 @@ def test_ctypes_structs_match_the_header_layout(tmp_path):
         for fname, _ in cls._fields_:
             want.append(f"{cname} {fname} {getattr(cls, fname).offset}")
     assert [g for g in got if g] == want
+
+
+def test_share53_single_tree_compiles_in_string_blocks():
+    """The 53-qubit single-amplitude tree (no slicing, largest tensor 2^28):
+    for the first 1024 of the 3*10^5 uniform strings the plan fits 270 GiB
+    by cutting the strings into a power-of-two number of blocks, and the
+    work per string stays at the single-amplitude cost (uniform strings
+    share only the smallest subtrees; Appendix C counts)."""
+    from synth import config_circuit, config_bitstrings
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "tests", "data", "share_53q_m14_single_plan.json")) as f:
+        fx = json.load(f)
+    assert fx["sliced"] == [] and fx["info"]["max_log2"] <= 28
+    c = config_circuit("share_53q_m14")
+    s = config_bitstrings("share_53q_m14", c.n_qubits)[:1024]
+    p = xeb.Plan(c, s, fx["children"], [], bind=False, memory_budget=270 << 30)
+    st = p.stats()
+    nb = st["n_blocks"]
+    assert st["workspace_bytes"] <= 270 << 30
+    assert nb >= 2 and nb & (nb - 1) == 0
+    per_string = st["cmacs_full"] / 1024
+    assert 0.9 * fx["info"]["cost"] <= per_string <= 1.01 * fx["info"]["cost"]

@@ -57,26 +57,29 @@ def test_share53_slice_partials_vs_oracle(precision):
 
 
 SINGLE = os.path.join(ROOT, "tests", "data", "share_53q_m14_single_plan.json")
+CROSS = 1e-4
 
 
 @pytest.mark.parametrize("precision", ["split_fp16", "c64"])
 def test_share53_single_tree_amplitudes_match_sliced_contraction(precision):
     """The single-amplitude tree at full size (53 qubits, 14 cycles, no
     slicing, strings in blocks under 270 GiB): complete amplitudes of the
-    first 16 strings equal the same tree's contraction with 4 sliced legs
+    first 64 strings equal the same tree's contraction with 4 sliced legs
     summed over its 16 slices (Appendix A, "Slicing": the sum over a sliced
     leg's values restores the contraction).  No FP64 value exists at this
     size; the two contractions share no partial tensor and each carries its
-    own FP32 rounding, so their difference is bounded by twice the
-    precision's bound against the exact amplitudes (at this depth the
-    sliced fixture's partials sit near 1e-5 of the oracle's in both forms)."""
+    own FP32 accumulation error, near 1e-5 normwise at this depth in both
+    forms (the sliced fixture's partials sit at 0.8-1.2e-5 of the oracle's;
+    the two trees here differ by 2.5e-5 in c64 and 2.9e-5 in split FP16).
+    The bound CROSS = 1e-4 leaves a margin of four over that; a dropped or
+    repeated slice would differ by O(1)."""
     from paper_2108_05665_amd import planner
 
     with open(SINGLE) as f:
         fx = json.load(f)
-    assert fx["sliced"] == [] and fx["info"]["max_log2"] <= 30
+    assert fx["sliced"] == [] and fx["info"]["max_log2"] <= 28
     circ = config_circuit("share_53q_m14")
-    strings = config_bitstrings("share_53q_m14", circ.n_qubits)[:16]
+    strings = config_bitstrings("share_53q_m14", circ.n_qubits)[:64]
     torch.cuda.empty_cache()
     p = xeb.Plan(circ, strings, fx["children"], [], precision=precision, memory_budget=270 * 2**30)
     assert p.stats()["n_blocks"] >= 2
@@ -103,4 +106,4 @@ def test_share53_single_tree_amplitudes_match_sliced_contraction(precision):
     assert np.all(np.isfinite(full)) and np.linalg.norm(sliced) > 0
     rel = float(np.linalg.norm(full - sliced) / np.linalg.norm(sliced))
     print(f"{precision}: single tree vs 16-slice contraction {rel:.2e}")
-    assert rel <= 2 * TOL[precision], rel
+    assert rel <= CROSS, rel
