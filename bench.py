@@ -807,6 +807,12 @@ def share53_single(args, circ, strings, precs) -> int:
         log(f"{prec}: plan for {k} strings compiled and bound in {t_plan:.1f} s, workspace "
             f"{st['workspace_bytes'] / 2**30:.1f} GiB, {st['n_blocks']} string blocks, "
             f"{st['cmacs_full']:.3e} complex MACs")
+        tune = None
+        if not args.no_autotune:
+            r = plan.autotune(reps=1)
+            tune = {k: r[k] for k in ("nodes_tuned", "nodes_changed", "candidates", "tuning_seconds")}
+            log(f"{prec}: autotuned {r['nodes_tuned']} nodes in {r['tuning_seconds']:.1f} s, "
+                f"{r['nodes_changed']} changed")
         amps = plan.new_amps()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -815,6 +821,25 @@ def share53_single(args, circ, strings, precs) -> int:
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         a = amps.cpu().numpy()
+        # Where the time goes: one more pass with the library's per-node
+        # events.
+        plan.set_profiling(True)
+        prof_amps = plan.new_amps()
+        plan.contract(prof_amps)
+        torch.cuda.synchronize()
+        nodes = []
+        for ns in plan.all_node_stats():
+            np_ = plan.read_node_profile(ns["node"])
+            if np_["launches"] == 0 or np_["seconds"] <= 0:
+                continue
+            nodes.append({"node": ns["node"], "kernel": ns["kernel"], "tile": ns["tile"],
+                          "keys": ns["variants"], "m_k_n_bits": [ns["m_bits"], ns["k_bits"], ns["n_bits"]],
+                          "launches": np_["launches"], "seconds": np_["seconds"],
+                          "algorithmic_tflops": 8.0 * np_["cmacs"] / np_["seconds"] / 1e12,
+                          "gbs": np_["bytes"] / np_["seconds"] / 1e9})
+        nodes.sort(key=lambda x: -x["seconds"])
+        plan.set_profiling(False)
+        del prof_amps
         pt = float(np.mean(np.ldexp(np.abs(a) ** 2, circ.n_qubits)))
         log(f"{prec}: {k} strings in {sec:.1f} s ({k / sec:.1f} amplitudes/s), XEB {F:.4f}, "
             f"mean 2^n|amp|^2 {pt:.4f}")
@@ -841,7 +866,8 @@ def share53_single(args, circ, strings, precs) -> int:
                          "cmacs": st["cmacs_full"],
                          "algorithmic_tflops": 8 * st["cmacs_full"] / sec / 1e12,
                          "n_blocks": st["n_blocks"], "workspace_gib": st["workspace_bytes"] / 2**30,
-                         "plan_s": t_plan, "xeb": F, "porter_thomas_mean": pt,
+                         "plan_s": t_plan, "autotune": tune, "top_nodes": nodes[:10],
+                         "xeb": F, "porter_thomas_mean": pt,
                          "sliced_check": {"strings": 8, "sliced_legs": len(sl), "rel_diff": diff}}
     head = results[precs[0]]
     out = {
