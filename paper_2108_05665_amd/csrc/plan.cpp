@@ -859,11 +859,17 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
     for (int T = L; T < nn; ++T) {
       const Node& nd = p.nodes[T];
       const NodeBlock& nb = blk.nodes[T - L];
+      // Output positions 0, 1, 2, ... taken by the first row (m) or column
+      // (n) bits: how many of the lowest output bits each side holds.
+      int run_m = 0, run_n = 0;
+      while (run_m < nd.mb && nd.posM[run_m] == run_m) ++run_m;
+      while (run_n < nd.nb && nd.posN[run_n] == run_n) ++run_n;
       std::fprintf(stderr,
                    "{\"node\":%d,\"left\":%d,\"right\":%d,\"variants\":%lld,\"m_bits\":%d,"
-                   "\"n_bits\":%d,\"k_bits\":%d,\"slice_mask\":%llu,\"kernel\":%d,\"blocks\":%zu}\n",
+                   "\"n_bits\":%d,\"k_bits\":%d,\"slice_mask\":%llu,\"kernel\":%d,\"blocks\":%zu,"
+                   "\"low_run_m\":%d,\"low_run_n\":%d}\n",
                    T, nd.left, nd.right, (long long)nb.nvar, nd.mb, nd.nb, nd.kb,
-                   (unsigned long long)nd.smask, nb.kernel, p.blocks.size());
+                   (unsigned long long)nd.smask, nb.kernel, p.blocks.size(), run_m, run_n);
     }
   }
 }
