@@ -224,6 +224,8 @@ def main() -> int:
                     help="share53: slices contracted (a contiguous block from slice 0)")
     ap.add_argument("--batch-budget-gib", type=float, default=None,
                     help="batch32: HBM workspace budget per circuit (default: a 32nd of 270 GiB)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave the batch workload out of the default run's record")
     ap.add_argument("--batch-max-seconds", type=float, default=2.0,
                     help="batch32: circuits whose best plan is estimated above this many "
                          "seconds per full contraction are planned but left out of the run")
@@ -477,13 +479,26 @@ def main() -> int:
         "xeb": r["F"],
         "cpu_baseline": None,
     }
+    if not args.no_batch and os.path.exists(BATCH_PLANS):
+        # The batch workload in the same record: its split-FP16 hipGraph form,
+        # one timed step.
+        with open(BATCH_PLANS) as f:
+            saved_batch = json.load(f)
+        b = run_batch(args, saved_batch, ["split_fp16"], 1)
+        out["batch32"] = {k: b[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "forms")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(oracle_net, oracle_pairs, strings, sliced, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 
 
-BATCH_SLICINGS = (6, 8, 10, 12, 16)
+BATCH_PLANS = os.path.join(ROOT, "tests", "data", "batch32_plans.json")
+BATCH_SLICINGS = (6, 10, 16)
+BATCH_SINGLE_SLICINGS = (0, 4, 8, 12, 16)
+BATCH_SINGLE_LOG2 = 26        # largest tensor of a single-string tree (2^26 complex = 512 MiB)
+BATCH_CMAC_RATE = 2.2e13      # complex MACs/s of a whole split-FP16 pass (36-qubit workload)
+BATCH_LAUNCH_S = 1e-5
+BATCH_PLAN_PROCS = 6          # circuits planned at once, one process each
 BATCH_HBM_GIB = 270.0  # of the 288 GB of HBM, what the batch's workspaces may take
 BATCH_MAX_STACK = 6
 
@@ -496,83 +511,19 @@ def batch_workload(i: int):
     return sp, circ, uniform_bitstrings(circ.n_qubits, sp["k"], sp["string_seed"])
 
 
-def batch_main(args) -> int:
-    """The batch workload: 32 circuits of 30-40 qubits (rectangular grids,
-    10-14 cycles) with 10^3-10^5 uniform strings each.  Every circuit is
-    planned against a per-circuit HBM budget (tree optimizer with the table
-    memory penalty, the slice count giving the lowest estimated time that
-    compiles within the budget).  A step is the contraction of all slices of
-    all circuits and their XEB: `value` is total amplitudes / s of one
-    launch of the whole batch as hipGraphs of at most 49152 nodes each (a
-    plan too large for one graph runs eagerly inside the step); a sequential
-    eager loop over the circuits is timed beside it.  Circuits estimated above --batch-max-seconds
-    (the deep 36-40 qubit ones need minutes to hours each on one GPU) are
-    listed with their estimates and left out of the launch."""
-    import numpy as np
-
-    # One launch holds all 32 circuits, so all their workspaces are resident at
-    # once: each circuit's budget is a 32nd of the HBM left for workspaces.
-    budget = int((args.batch_budget_gib if args.batch_budget_gib else BATCH_HBM_GIB / 32) * 2**30)
-    if args.plan_only:
-        from paper_2108_05665_amd import planner, xeb
-
-        plans = []
-        for i in range(32):
-            sp, circ, strings = batch_workload(i)
-            best = None
-            for ns in BATCH_SLICINGS:
-                ch, sl, info = planner.plan(circ, strings, n_sliced=ns, trials=8, seed=0,
-                                            anneal_steps=100000, anneal_restarts=4, workers=4,
-                                            table_bytes_max=budget)
-                try:
-                    st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
-                except xeb.XebError:
-                    continue
-                if best is None or info["seconds"] < best["info"]["seconds"]:
-                    best = {"i": i, "children": [[int(a), int(b)] for a, b in ch],
-                            "sliced": [int(x) for x in sl], "info": info,
-                            "workspace_bytes": int(st["workspace_bytes"]),
-                            "n_blocks": int(st["n_blocks"])}
-            if best is None:
-                log(f"circuit {i}: no slicing in {BATCH_SLICINGS} fits {budget} bytes")
-                plans.append({"i": i, "included": False, "reason": "no plan within the budget"})
-                continue
-            # Stack the low slice bits as far as the budget allows without more
-            # string blocks (at most 2^6 slices per launch).
-            J, stj = planner.choose_stacking(circ, strings, best["children"], best["sliced"], budget,
-                                             max_stack=BATCH_MAX_STACK, max_blocks=best["n_blocks"])
-            best["stack_slices"] = J
-            if J:
-                best["workspace_bytes"] = int(stj["workspace_bytes"])
-            best["included"] = best["info"]["seconds"] <= args.batch_max_seconds
-            if not best["included"]:
-                best["reason"] = "estimated above --batch-max-seconds"
-            log(f"circuit {i}: {circ.n_qubits} qubits, {sp['cycles']} cycles, k={sp['k']}, "
-                f"s={len(best['sliced'])}, J={J}, estimated {best['info']['seconds']:.3f} s"
-                f"{'' if best['included'] else ' (left out)'}")
-            plans.append(best)
-        with open(args.plan_only, "w") as f:
-            json.dump({"workload": "batch32", "budget": budget,
-                       "max_seconds": args.batch_max_seconds, "plans": plans}, f)
-        return 0
-    if not args.tree:
-        print("batch32 needs --tree PATH from a --plan-only run (planning takes minutes)",
-              file=sys.stderr)
-        return 2
+def run_batch(args, saved, precs, steps: int) -> dict:
+    """Runs the batch plans `saved` (as written by --plan-only) whose
+    estimate is within --batch-max-seconds, in the precisions `precs`, and
+    returns the result record."""
     import torch
     from paper_2108_05665_amd import xeb
-
-    with open(args.tree) as f:
-        saved = json.load(f)
-    assert saved["workload"] == "batch32"
 
     def included(rec):
         # Every circuit with a plan within the budget, estimated at most
         # --batch-max-seconds per contraction (the run's cap).
-        return "children" in rec and rec["info"]["seconds"] <= args.batch_max_seconds
+        return "children" in rec and rec["estimated_s"] <= args.batch_max_seconds
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     total_k = 0
     specs = []
     results = {}
@@ -583,15 +534,18 @@ def batch_main(args) -> int:
                 continue
             sp, circ, strings = batch_workload(rec["i"])
             plan = xeb.Plan(circ, strings, rec["children"], rec["sliced"], precision=prec,
-                            memory_budget=saved["budget"], stack_slices=rec.get("stack_slices", 0))
+                            memory_budget=rec.get("budget_bytes", saved["budget"]),
+                            stack_slices=rec.get("stack_slices", 0))
             if not args.no_autotune:
                 plan.autotune(reps=2)
             plans.append(plan)
             amps.append(plan.new_amps())
             if prec == precs[0]:
                 total_k += len(strings)
-                specs.append({"qubits": circ.n_qubits, "cycles": sp["cycles"], "strings": sp["k"],
-                              "slices": 1 << len(rec["sliced"])})
+                specs.append({"circuit": rec["i"], "qubits": circ.n_qubits, "cycles": sp["cycles"],
+                              "strings": sp["k"], "tree": rec.get("tree"),
+                              "slices": 1 << len(rec["sliced"]), "stacked": rec.get("stack_slices", 0),
+                              "string_blocks": rec.get("n_blocks"), "estimated_s": rec.get("estimated_s")})
         log(f"{prec}: {len(plans)} plans bound, "
             f"{sum(p.stats()['workspace_bytes'] for p in plans) / 2**30:.1f} GiB of workspace")
 
@@ -614,12 +568,12 @@ def batch_main(args) -> int:
         batch.fidelities()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(steps):
             batch.launch()
-            log(f"{prec}: graph step {k + 1}/{args.steps} launched")
+            log(f"{prec}: graph step {k + 1}/{steps} launched")
         F = batch.fidelities()
         torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
+        sec = (time.perf_counter() - t0) / steps
         same = all(torch.equal(a.cpu(), b) for a, b in zip(amps, eager_amps))
         log(f"{prec}: graph {sec:.2f} s per batch ({total_k / sec:.0f} amplitudes/s), "
             f"graph == eager: {same}")
@@ -637,7 +591,7 @@ def batch_main(args) -> int:
         "value": total_k / head["sec"],
         "unit": "amplitudes/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": 1,
         "ms_per_step": 1e3 * head["sec"],
         "higher_is_better": True,
@@ -646,13 +600,14 @@ def batch_main(args) -> int:
         "dtype": DTYPE[precs[0]],
         "data": "synthetic",
         "config": {"workload": "batch32: 32 circuits, 30-40 qubits on rectangular grids, 10-14 "
-                               "cycles, 10^3-10^5 uniform strings each, sliced to a per-circuit "
-                               "HBM budget; the circuits estimated above "
+                               "cycles, 10^3-10^5 uniform strings each, each planned within a 32nd "
+                               "of 270 GiB (a tree for one string with the strings in blocks, or "
+                               "one for all strings); the circuits estimated above "
                                f"{args.batch_max_seconds} s per contraction left out",
                    "strings": total_k, "budget_gib_per_circuit": saved["budget"] / 2**30,
                    "circuits": specs,
                    "left_out": [{"circuit": r["i"],
-                                 "estimated_s": r.get("info", {}).get("seconds"),
+                                 "estimated_s": r.get("estimated_s"),
                                  "reason": "estimated above the cap" if "children" in r
                                  else "no plan within the budget"}
                                 for r in saved["plans"] if not included(r)]},
@@ -664,6 +619,131 @@ def batch_main(args) -> int:
                          "xeb": r["F"]}
                   for prec, r in results.items()},
     }
+    return out
+
+
+def _batch_estimate(st) -> float:
+    # Seconds on one GPU: complex MACs at the split form's measured
+    # whole-pass rate plus a fixed cost per kernel launch.
+    return st["cmacs_full"] / BATCH_CMAC_RATE + st["evals_full"] * BATCH_LAUNCH_S
+
+
+def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
+    """Plan circuit i of the batch within `budget` bytes (a process of the
+    planning pool): the cheaper by estimated time of (a) the tree annealed
+    for one string (uniform strings share little) with the fewest sliced legs
+    that compile, the strings cut into blocks by the plan compiler, and (b)
+    a greedy tree for all strings at once (shared subtrees evaluated once per
+    key) at a few slice counts."""
+    from paper_2108_05665_amd import planner, xeb
+
+    sp, circ, strings = batch_workload(i)
+    cands = []
+    for ns in BATCH_SINGLE_SLICINGS:
+        ch, sl, info = planner.plan(circ, strings[:1], n_sliced=ns, trials=8, seed=1,
+                                    anneal_steps=1_000_000, anneal_restarts=2, workers=1,
+                                    anneal_objective="paper", size_log2_max=BATCH_SINGLE_LOG2)
+        try:
+            st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
+        except xeb.XebError:
+            continue
+        cands.append(("single", ch, sl, info, st))
+        break
+    for ns in BATCH_SLICINGS:
+        ch, sl, info = planner.plan(circ, strings, n_sliced=ns, trials=4, seed=0, table_bytes_max=budget)
+        try:
+            st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
+        except xeb.XebError:
+            continue
+        cands.append(("multi", ch, sl, info, st))
+    if not cands:
+        return {"i": i, "included": False, "reason": "no plan within the budget",
+                "log": f"circuit {i}: no plan fits {budget} bytes"}
+    kind, ch, sl, info, st = min(cands, key=lambda c: _batch_estimate(c[4]))
+    best = {"i": i, "tree": kind, "children": [[int(a), int(b)] for a, b in ch],
+            "sliced": [int(x) for x in sl], "info": info,
+            "workspace_bytes": int(st["workspace_bytes"]), "n_blocks": int(st["n_blocks"]),
+            "cmacs_full": float(st["cmacs_full"]), "evals_full": float(st["evals_full"]),
+            "estimated_s": _batch_estimate(st),
+            "candidates": [{"tree": c[0], "sliced": len(c[2]), "estimated_s": _batch_estimate(c[4]),
+                            "cmacs_full": float(c[4]["cmacs_full"]), "n_blocks": int(c[4]["n_blocks"])}
+                           for c in cands]}
+    # Stack the low slice bits as far as the budget allows without more
+    # string blocks (at most 2^6 slices per launch).
+    J, stj = planner.choose_stacking(circ, strings, best["children"], best["sliced"], budget,
+                                     max_stack=BATCH_MAX_STACK, max_blocks=best["n_blocks"])
+    best["stack_slices"] = J
+    if J:
+        best.update(workspace_bytes=int(stj["workspace_bytes"]), evals_full=float(stj["evals_full"]),
+                    estimated_s=_batch_estimate(stj))
+    best["included"] = best["estimated_s"] <= max_seconds
+    if not best["included"]:
+        best["reason"] = "estimated above --batch-max-seconds"
+    best["log"] = (f"circuit {i}: {circ.n_qubits} qubits, {sp['cycles']} cycles, k={sp['k']}, {kind} tree, "
+                   f"s={len(best['sliced'])}, J={J}, {best['n_blocks']} blocks, "
+                   f"estimated {best['estimated_s']:.3f} s")
+    return best
+
+
+def batch_main(args) -> int:
+    """The batch workload: 32 circuits of 30-40 qubits (rectangular grids,
+    10-14 cycles) with 10^3-10^5 uniform strings each.  Every circuit is
+    planned against a per-circuit HBM budget of a 32nd of 270 GiB (all
+    circuits resident for one launch): the cheaper by estimated time of a
+    tree annealed for one string (fewest sliced legs that compile, strings
+    cut into blocks) and a greedy tree for all strings at once (a few slice
+    counts); then HBM left unused goes to the costliest plans while it cuts
+    their string blocks.  A step is the contraction of all slices of
+    all circuits and their XEB: `value` is total amplitudes / s of one
+    launch of the whole batch as hipGraphs of at most 49152 nodes each (a
+    plan too large for one graph runs eagerly inside the step); a sequential
+    eager loop over the circuits is timed beside it.  Circuits estimated above --batch-max-seconds
+    (the deep 36-40 qubit ones need minutes to hours each on one GPU) are
+    listed with their estimates and left out of the launch."""
+    import numpy as np
+
+    # One launch holds all 32 circuits, so all their workspaces are resident at
+    # once: each circuit's budget is a 32nd of the HBM left for workspaces.
+    budget = int((args.batch_budget_gib if args.batch_budget_gib else BATCH_HBM_GIB / 32) * 2**30)
+    if args.plan_only:
+        import multiprocessing as mp
+
+        from paper_2108_05665_amd import xeb
+
+        with mp.get_context("fork").Pool(BATCH_PLAN_PROCS) as pool:
+            plans = pool.starmap(_batch_plan_one, [(i, budget, args.batch_max_seconds) for i in range(32)])
+        for rec in plans:
+            log(rec["log"])
+        # All circuits are resident in one launch: the HBM the plans leave
+        # unused goes to the costliest ones, as long as it cuts their string
+        # blocks (fewer blocks: fewer launches, less repeated work).
+        spare = int(BATCH_HBM_GIB * 2**30) - sum(r["workspace_bytes"] for r in plans if "children" in r)
+        for rec in sorted((r for r in plans if "children" in r), key=lambda r: -r["estimated_s"]):
+            if spare <= 0 or rec["n_blocks"] == 1:
+                continue
+            sp, circ, strings = batch_workload(rec["i"])
+            b2 = rec["workspace_bytes"] + spare
+            st2 = xeb.Plan(circ, strings, rec["children"], rec["sliced"], memory_budget=b2, bind=False,
+                           stack_slices=rec["stack_slices"]).stats()
+            if st2["n_blocks"] < rec["n_blocks"]:
+                spare -= int(st2["workspace_bytes"]) - rec["workspace_bytes"]
+                log(f"circuit {rec['i']}: {rec['n_blocks']} -> {st2['n_blocks']} string blocks with "
+                    f"{b2 / 2**30:.1f} GiB")
+                rec.update(budget_bytes=int(b2), workspace_bytes=int(st2["workspace_bytes"]),
+                           n_blocks=int(st2["n_blocks"]), cmacs_full=float(st2["cmacs_full"]),
+                           evals_full=float(st2["evals_full"]), estimated_s=_batch_estimate(st2))
+        with open(args.plan_only, "w") as f:
+            json.dump({"workload": "batch32", "budget": budget,
+                       "max_seconds": args.batch_max_seconds, "plans": plans}, f)
+        return 0
+    if not args.tree:
+        print("batch32 needs --tree PATH from a --plan-only run (planning takes minutes)",
+              file=sys.stderr)
+        return 2
+    with open(args.tree) as f:
+        saved = json.load(f)
+    assert saved["workload"] == "batch32"
+    out = run_batch(args, saved, [p.strip() for p in args.precisions.split(",") if p.strip()], args.steps)
     print(json.dumps(out), flush=True)
     return 0
 
