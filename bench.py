@@ -521,7 +521,8 @@ def run_batch(args, saved, precs, steps: int) -> dict:
     def included(rec):
         # Every circuit with a plan within the budget, estimated at most
         # --batch-max-seconds per contraction (the run's cap).
-        return "children" in rec and rec["estimated_s"] <= args.batch_max_seconds
+        est = rec.get("estimated_s", rec.get("info", {}).get("seconds", float("inf")))
+        return "children" in rec and est <= args.batch_max_seconds
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     total_k = 0
