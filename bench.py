@@ -224,6 +224,8 @@ def main() -> int:
                     help="share53: slices contracted (a contiguous block from slice 0)")
     ap.add_argument("--batch-budget-gib", type=float, default=None,
                     help="batch32: HBM workspace budget per circuit (default: a 32nd of 270 GiB)")
+    ap.add_argument("--batch-skip", default="",
+                    help="batch32 --plan-only: circuits (comma-separated) left unplanned")
     ap.add_argument("--no-batch", action="store_true",
                     help="leave the batch workload out of the default run's record")
     ap.add_argument("--batch-max-seconds", type=float, default=2.0,
@@ -494,11 +496,12 @@ def main() -> int:
 
 BATCH_PLANS = os.path.join(ROOT, "tests", "data", "batch32_plans.json")
 BATCH_SLICINGS = (6, 10, 16)
-BATCH_SINGLE_SLICINGS = (0, 4, 8, 12, 16)
+BATCH_SINGLE_SLICINGS = (0, 4, 8)
 BATCH_SINGLE_LOG2 = 26        # largest tensor of a single-string tree (2^26 complex = 512 MiB)
 BATCH_CMAC_RATE = 2.2e13      # complex MACs/s of a whole split-FP16 pass (36-qubit workload)
 BATCH_LAUNCH_S = 1e-5
 BATCH_PLAN_PROCS = 6          # circuits planned at once, one process each
+BATCH_MULTI_MAX_STRINGS = 30000  # all-strings trees only for batches up to this size
 BATCH_HBM_GIB = 270.0  # of the 288 GB of HBM, what the batch's workspaces may take
 BATCH_MAX_STACK = 6
 
@@ -629,6 +632,23 @@ def _batch_estimate(st) -> float:
     return st["cmacs_full"] / BATCH_CMAC_RATE + st["evals_full"] * BATCH_LAUNCH_S
 
 
+def _batch_plan_part(i: int, budget: int, max_seconds: float, parts: str, skip: bool = False) -> dict:
+    if skip:
+        return {"i": i, "included": False, "reason": "not planned (--batch-skip)",
+                "log": f"circuit {i}: not planned (--batch-skip)"}
+    path = os.path.join(parts, f"{i}.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("budget") == budget:
+            return rec["plan"]
+    rec = _batch_plan_one(i, budget, max_seconds)
+    with open(path + ".tmp", "w") as f:
+        json.dump({"budget": budget, "plan": rec}, f)
+    os.replace(path + ".tmp", path)
+    return rec
+
+
 def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
     """Plan circuit i of the batch within `budget` bytes (a process of the
     planning pool): the cheaper by estimated time of (a) the tree annealed
@@ -639,6 +659,7 @@ def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
     from paper_2108_05665_amd import planner, xeb
 
     sp, circ, strings = batch_workload(i)
+    t0 = time.perf_counter()
     cands = []
     for ns in BATCH_SINGLE_SLICINGS:
         ch, sl, info = planner.plan(circ, strings[:1], n_sliced=ns, trials=8, seed=1,
@@ -650,13 +671,17 @@ def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
             continue
         cands.append(("single", ch, sl, info, st))
         break
+    log(f"circuit {i}: single-string tree done at {time.perf_counter() - t0:.0f} s")
     for ns in BATCH_SLICINGS:
+        if len(strings) > BATCH_MULTI_MAX_STRINGS:
+            break
         ch, sl, info = planner.plan(circ, strings, n_sliced=ns, trials=4, seed=0, table_bytes_max=budget)
         try:
             st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
         except xeb.XebError:
             continue
         cands.append(("multi", ch, sl, info, st))
+        log(f"circuit {i}: all-strings tree at s = {ns} done at {time.perf_counter() - t0:.0f} s")
     if not cands:
         return {"i": i, "included": False, "reason": "no plan within the budget",
                 "log": f"circuit {i}: no plan fits {budget} bytes"}
@@ -670,9 +695,13 @@ def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
                             "cmacs_full": float(c[4]["cmacs_full"]), "n_blocks": int(c[4]["n_blocks"])}
                            for c in cands]}
     # Stack the low slice bits as far as the budget allows without more
-    # string blocks (at most 2^6 slices per launch).
-    J, stj = planner.choose_stacking(circ, strings, best["children"], best["sliced"], budget,
-                                     max_stack=BATCH_MAX_STACK, max_blocks=best["n_blocks"])
+    # string blocks (at most 2^6 slices per launch).  A plan that already
+    # cuts its strings into blocks would need more of them (stacked tables
+    # are 2^J times larger), so only one-block plans try.
+    J, stj = 0, None
+    if best["sliced"] and best["n_blocks"] == 1:
+        J, stj = planner.choose_stacking(circ, strings, best["children"], best["sliced"], budget,
+                                         max_stack=BATCH_MAX_STACK, max_blocks=1)
     best["stack_slices"] = J
     if J:
         best.update(workspace_bytes=int(stj["workspace_bytes"]), evals_full=float(stj["evals_full"]),
@@ -711,8 +740,14 @@ def batch_main(args) -> int:
 
         from paper_2108_05665_amd import xeb
 
+        # Each circuit's plan is also kept in PATH.parts/ as it completes, so an
+        # interrupted run resumes where it stopped.
+        parts = args.plan_only + ".parts"
+        os.makedirs(parts, exist_ok=True)
+        skip = {int(x) for x in args.batch_skip.split(",") if x.strip()}
         with mp.get_context("fork").Pool(BATCH_PLAN_PROCS) as pool:
-            plans = pool.starmap(_batch_plan_one, [(i, budget, args.batch_max_seconds) for i in range(32)])
+            plans = pool.starmap(_batch_plan_part,
+                                 [(i, budget, args.batch_max_seconds, parts, i in skip) for i in range(32)])
         for rec in plans:
             log(rec["log"])
         # All circuits are resident in one launch: the HBM the plans leave
@@ -735,6 +770,9 @@ def batch_main(args) -> int:
                            evals_full=float(st2["evals_full"]), estimated_s=_batch_estimate(st2))
         with open(args.plan_only, "w") as f:
             json.dump({"workload": "batch32", "budget": budget,
+                       "made_by": "python bench.py --workload batch32 --plan-only PATH "
+                                  f"--batch-max-seconds {args.batch_max_seconds:g}"
+                                  + (f" --batch-skip {args.batch_skip}" if args.batch_skip else ""),
                        "max_seconds": args.batch_max_seconds, "plans": plans}, f)
         return 0
     if not args.tree:
