@@ -497,9 +497,12 @@ def main() -> int:
 BATCH_PLANS = os.path.join(ROOT, "tests", "data", "batch32_plans.json")
 BATCH_SLICINGS = (6, 10, 16)
 BATCH_SINGLE_SLICINGS = (0, 4, 8)
-BATCH_SINGLE_LOG2 = 26        # largest tensor of a single-string tree (2^26 complex = 512 MiB)
+BATCH_SINGLE_LOG2 = (24, 26)  # largest tensors tried for a one-string tree (2^24, 2^26 complex):
+                              # smaller ones cost more per string but let more strings share a block
 BATCH_CMAC_RATE = 2.2e13      # complex MACs/s of a whole split-FP16 pass (36-qubit workload)
-BATCH_LAUNCH_S = 1e-5
+BATCH_LAUNCH_S = 8e-5         # per launch: small string blocks leave the kernels latency-bound
+                              # (the batch ran 2-2.4 times its MAC-rate estimate, ~70-100 us
+                              # per launch beyond it)
 BATCH_PLAN_PROCS = 6          # circuits planned at once, one process each
 BATCH_MULTI_MAX_STRINGS = 30000  # all-strings trees only for batches up to this size
 BATCH_HBM_GIB = 270.0  # of the 288 GB of HBM, what the batch's workspaces may take
@@ -661,16 +664,17 @@ def _batch_plan_one(i: int, budget: int, max_seconds: float) -> dict:
     sp, circ, strings = batch_workload(i)
     t0 = time.perf_counter()
     cands = []
-    for ns in BATCH_SINGLE_SLICINGS:
-        ch, sl, info = planner.plan(circ, strings[:1], n_sliced=ns, trials=8, seed=1,
-                                    anneal_steps=1_000_000, anneal_restarts=2, workers=1,
-                                    anneal_objective="paper", size_log2_max=BATCH_SINGLE_LOG2)
-        try:
-            st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
-        except xeb.XebError:
-            continue
-        cands.append(("single", ch, sl, info, st))
-        break
+    for log2 in BATCH_SINGLE_LOG2:
+        for ns in BATCH_SINGLE_SLICINGS:
+            ch, sl, info = planner.plan(circ, strings[:1], n_sliced=ns, trials=8, seed=1,
+                                        anneal_steps=1_000_000, anneal_restarts=2, workers=1,
+                                        anneal_objective="paper", size_log2_max=log2)
+            try:
+                st = xeb.Plan(circ, strings, ch, sl, memory_budget=budget, bind=False).stats()
+            except xeb.XebError:
+                continue
+            cands.append(("single", ch, sl, info, st))
+            break
     log(f"circuit {i}: single-string tree done at {time.perf_counter() - t0:.0f} s")
     for ns in BATCH_SLICINGS:
         if len(strings) > BATCH_MULTI_MAX_STRINGS:
