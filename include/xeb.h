@@ -172,8 +172,13 @@ typedef struct {
   int32_t m_bits, n_bits, k_bits; /* free legs of left, free legs of right, shared legs */
   uint64_t slice_mask;       /* bit j set: the node depends on sliced leg j */
   int32_t kernel;            /* XEB_KERNEL_* (first block) */
-  int32_t swapped;           /* 1: the kernel runs with the right child as the row operand */
-  int32_t tile;              /* MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256, 3 = 64x16,
+  int32_t swapped;           /* 1: the kernel runs with the right child as the row operand
+                                (per-element kernel, row-streaming form: 1 = the left
+                                child's rows are streamed, 0 = the right child's) */
+  int32_t tile;              /* per-element kernel: -1 = one thread per output element,
+                                -2 = row-streaming form (K <= 16, streamed side >= 8 bits,
+                                other side <= 6 bits);
+                                MFMA tile shape: 0 = 64x64, 1 = 32x128, 2 = 16x256, 3 = 64x16,
                                 4 = 128x128, 5 = 128x128 on eight waves with double-
                                 buffered LDS (split forms), 6 = 128x128 and 7 = 256x128
                                 on operands converted to hi/lo planes first (split
@@ -387,7 +392,10 @@ int xeb_plan_autotune(xeb_plan_t plan, int32_t reps, void* stream, xeb_autotune_
  * A node's kernel configuration (as reported by xeb_plan_node_stats), for
  * reading the autotuner's choices and applying them, or any valid
  * configuration, to a plan with the same tree.  kernel: XEB_KERNEL_GENERIC
- * (the other fields are ignored) or XEB_KERNEL_MFMA with tile 0..5, swapped
+ * with tile -2 (row-streaming form, swapped naming the streamed side as in
+ * xeb_node_stats_t; XEB_EINVAL where the shape does not fit it) or any other
+ * tile (one thread per output element; the remaining fields are ignored), or
+ * XEB_KERNEL_MFMA with tile 0..7, swapped
  * 0/1 (right child as the row operand), ksplit a power of two with K / ksplit
  * >= k_slab, k_slab 16 / 32 (complex64) or 32 / 64 (split forms; 16 on tile
  * 5, which takes no complex64), k_groups 1 or 2 (2 and the larger slab only

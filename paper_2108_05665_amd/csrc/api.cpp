@@ -222,8 +222,8 @@ int xeb_plan_node_stats(xeb_plan_t plan, int32_t node, xeb_node_stats_t* st) {
     st->slice_mask = (nd.smask << p.sj) | stacked;
     const xeb::NodeBlock& nb = p.blocks.front().nodes[node - p.n_leaves];
     st->kernel = nb.kernel;
-    st->swapped = nb.kernel == XEB_KERNEL_MFMA ? nb.swapped : 0;
-    st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : -1;
+    st->swapped = nb.kernel == XEB_KERNEL_MFMA || nb.tile == 1 ? nb.swapped : 0;
+    st->tile = nb.kernel == XEB_KERNEL_MFMA ? nb.tile : (nb.tile == 1 ? -2 : -1);
     st->ksplit = nb.kernel == XEB_KERNEL_MFMA ? nb.ksplit : 1;
     st->k_slab = nb.kernel == XEB_KERNEL_MFMA ? nb.tk : 0;
     st->k_groups = nb.kernel == XEB_KERNEL_MFMA ? nb.kg : 0;

@@ -18,22 +18,28 @@ namespace {
 struct Candidate {
   int kernel, tile, swapped, ksplit, tk, kg, keyed;
   bool operator==(const Candidate& o) const {
-    return kernel == o.kernel && (kernel == XEB_KERNEL_GENERIC ||
-                                  (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit &&
-                                   tk == o.tk && kg == o.kg && keyed == o.keyed));
+    return kernel == o.kernel &&
+           (kernel == XEB_KERNEL_GENERIC
+                ? (tile == o.tile && swapped == o.swapped)
+                : (tile == o.tile && swapped == o.swapped && ksplit == o.ksplit && tk == o.tk &&
+                   kg == o.kg && keyed == o.keyed));
   }
 };
 
+// (Per-element kernel: tile 0 = one thread per output element, tile 1 = the
+// row-streaming form with `swapped` naming the stream side.)
 constexpr Candidate kGeneric{XEB_KERNEL_GENERIC, 0, 0, 1, 0, 1, 0};
 
+Candidate generic_rows(int stream_l) { return {XEB_KERNEL_GENERIC, 1, stream_l, 1, 0, 1, 0}; }
+
 Candidate current(const NodeBlock& nb) {
-  if (nb.kernel == XEB_KERNEL_GENERIC) return kGeneric;
+  if (nb.kernel == XEB_KERNEL_GENERIC) return {XEB_KERNEL_GENERIC, nb.tile, nb.swapped, 1, 0, 1, 0};
   return {XEB_KERNEL_MFMA, nb.tile, nb.swapped, nb.ksplit, nb.tk, nb.kg, nb.keyed};
 }
 
 void apply(const Node& nd, int64_t nl, int64_t nr, NodeBlock& nb, const Candidate& c) {
   if (c.kernel == XEB_KERNEL_GENERIC)
-    configure_generic(nb);
+    configure_generic(nb, c.tile, c.swapped);
   else
     configure_mfma(nd, nl, nr, nb, c.tile, c.swapped, c.ksplit, c.tk, c.kg, c.keyed);
 }
@@ -52,7 +58,11 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   // The per-element kernel cannot win on large contractions; leave those out
   // to bound the tuning time.
-  if (useful <= std::ldexp(1.0, 30)) out.push_back(kGeneric);
+  if (useful <= std::ldexp(1.0, 30)) {
+    out.push_back(kGeneric);
+    for (int sl = 0; sl < 2; ++sl)
+      if (generic_rows_ok(nd, sl)) out.push_back(generic_rows(sl));
+  }
   const int64_t K = int64_t(1) << nd.kb;
   // Keyed form: the only MFMA form of a node too sparse to stack, and an
   // alternative to the pair table (which multiplies up to 8x the useful
@@ -117,6 +127,8 @@ xeb_node_config_t get_node_config(const Plan* p, int T) {
     c.k_groups = nb.kg;
     c.keyed = nb.pair_mode == 2 ? 1 : 0;
   } else {
+    c.tile = nb.tile == 1 ? -2 : -1;
+    c.swapped = nb.tile == 1 ? nb.swapped : 0;
     c.ksplit = 1;
     c.k_groups = 1;
   }
@@ -126,9 +138,18 @@ xeb_node_config_t get_node_config(const Plan* p, int T) {
 void set_node_config(Plan* p, int T, const xeb_node_config_t& cfg) {
   if (p->capturing) fail(XEB_ESTATE, "cannot change a node while a batch is being captured");
   Candidate c{cfg.kernel, cfg.tile, cfg.swapped, cfg.ksplit, cfg.k_slab, cfg.k_groups, cfg.keyed};
-  if (c.kernel == XEB_KERNEL_GENERIC) c = kGeneric;
-  if (c.kernel == XEB_KERNEL_MFMA && c.keyed != 0 && c.keyed != 1) fail(XEB_EINVAL, "keyed must be 0 or 1");
   const Node& nd = p->nodes[T];
+  if (c.kernel == XEB_KERNEL_GENERIC) {
+    if (cfg.tile == -2) {
+      if (cfg.swapped != 0 && cfg.swapped != 1) fail(XEB_EINVAL, "invalid stream side");
+      if (!generic_rows_ok(nd, cfg.swapped))
+        fail(XEB_EINVAL, "the row-streaming form does not fit the node with that stream side");
+      c = generic_rows(cfg.swapped);
+    } else {
+      c = kGeneric;
+    }
+  }
+  if (c.kernel == XEB_KERNEL_MFMA && c.keyed != 0 && c.keyed != 1) fail(XEB_EINVAL, "keyed must be 0 or 1");
   const int64_t K = int64_t(1) << nd.kb;
   if (c.kernel == XEB_KERNEL_MFMA) {
     if (c.tile < 0 || c.tile >= kMfmaTiles || (c.swapped != 0 && c.swapped != 1))

@@ -87,7 +87,18 @@ constexpr int kAmaxStride = 16;  // words between slots (one 128-byte line each)
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 void take_launch_events(hipEvent_t* start, hipEvent_t* stop);
 
+// The per-element contraction.  a.tile 0: one output element per thread (any
+// shape); a.tile 1: the row-streaming form (a.swapped 0 streams R's rows, 1
+// streams L's), for the shapes generic_rows_fit accepts.
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
+// Stream rows per thread in the row-streaming form (log2), where the stream
+// side has at least 8 + kRowsLog2U bits (one row per thread below that).
+constexpr int kRowsLog2U = 2;
+// The row-streaming form runs K = 2^kb <= 16, a stream side of at least 8
+// bits (256 rows per work item) and at most 64 broadcast rows.
+inline bool generic_rows_fit(int kb, int stream_bits, int bcast_bits) {
+  return kb >= 0 && kb <= 4 && stream_bits >= 8 && bcast_bits >= 0 && bcast_bits <= 6;
+}
 // The MFMA contraction; with a.ksplit > 1 it writes the chunk partials only
 // and launch_splitk_reduce (same arguments, same stream, right after) sums
 // them and writes T.

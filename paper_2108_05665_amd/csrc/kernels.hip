@@ -15,6 +15,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <stdexcept>
 
 #include "compensated.h"
@@ -233,6 +234,81 @@ __global__ void __launch_bounds__(256) k_contract_generic(ContractArgs g) {
                                 g.B + int64_t(g.ridx[a]) * sizeB + (n << g.kb), g.kb);
       g.C[e] = v;
       amax = fmaxf(amax, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+  }
+  if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
+}
+
+// Row-streaming form of the per-element contraction, for a short contracted
+// leg (K = 2^KB <= 16) between a wide side (the stream side, >= 8 bits) and a
+// narrow one (the broadcast side).  A work item is one key and 256 U
+// consecutive stream rows: each thread loads its U rows of K complex once
+// into registers, then walks the broadcast side's 2^bb rows, whose addresses
+// are wave-uniform (scalar loads), and stores one output per (row, b).  The
+// per-element form instead loads both K-long rows for every output element,
+// which makes it bound by the vector cache rather than by HBM.  Items run key
+// fastest, so the keys that share a stream variant read its rows together.
+// g.swapped: 0 = the stream side is R (columns n), 1 = it is L (rows m).
+template <int KB, int U>
+__global__ void __launch_bounds__(256) k_contract_rows(ContractArgs g) {
+  constexpr int K = 1 << KB;
+  float amax = 0.f;
+  const bool sm = g.swapped != 0;
+  const float2* S = sm ? g.A : g.B;
+  const float2* Bc = sm ? g.B : g.A;
+  const int32_t* sidx = sm ? g.lidx : g.ridx;
+  const int32_t* bidx = sm ? g.ridx : g.lidx;
+  const int sbits = sm ? g.mb : g.nb, bbits = sm ? g.nb : g.mb;
+  const BitMap& mapS = sm ? g.mapM : g.mapN;
+  const BitMap& mapB = sm ? g.mapN : g.mapM;
+  const int64_t per = int64_t(1) << (g.mb + g.nb);
+  const int64_t chunks = (int64_t(1) << sbits) / (256 * U);
+  const int64_t items = g.nvar * chunks;
+  const int64_t dep_t = deposit(threadIdx.x, mapS);
+  int64_t dep_u[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) dep_u[u] = deposit(uint64_t(u) << 8, mapS) + dep_t;
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const int64_t a = w % g.nvar, c = w / g.nvar;
+    const int ai = __builtin_amdgcn_readfirstlane(int(a));
+    const uint32_t sv = load_uniform(sidx + ai), bv = load_uniform(bidx + ai);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t s0 = c * (256 * U);
+    const float2* srow = S + ((uint64_t(sv) << sbits) + s0 + threadIdx.x) * K;
+    float2 x[U][K];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (KB == 0) {
+        x[u][0] = srow[(u << 8) * K];
+      } else {
+#pragma unroll
+        for (int j = 0; j < K / 2; ++j) {
+          const float4 q = reinterpret_cast<const float4*>(srow + (u << 8) * K)[j];
+          x[u][2 * j] = make_float2(q.x, q.y);
+          x[u][2 * j + 1] = make_float2(q.z, q.w);
+        }
+      }
+    }
+    float2* out = g.C + a * per + deposit(uint64_t(s0), mapS);
+    const float2* brow0 = Bc + (uint64_t(bv) << (bbits + KB));
+    for (int b = 0; b < (1 << bbits); ++b) {
+      // (The broadcast row is the same for the whole wave: scalar loads.)
+      const auto* brow = (const __attribute__((address_space(4))) float*)(brow0 + b * K);
+      float2 y[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) y[k] = make_float2(brow[2 * k], brow[2 * k + 1]);
+      const int64_t db = deposit(uint64_t(b), mapB);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          re += x[u][k].x * y[k].x - x[u][k].y * y[k].y;
+          im += x[u][k].x * y[k].y + x[u][k].y * y[k].x;
+        }
+        out[db + dep_u[u]] = make_float2(re, im);
+        amax = fmaxf(amax, fmaxf(fabsf(re), fabsf(im)));
+      }
     }
   }
   if (g.amax_out) publish_amax(amax, g.amax_out, g.epoch);
@@ -1716,6 +1792,31 @@ void take_launch_events(hipEvent_t* start, hipEvent_t* stop) {
 void launch_contract_generic(const ContractArgs& a, hipStream_t s) {
   const int64_t total = a.nvar << (a.mb + a.nb);
   if (total <= 0) return;
+  if (a.tile == 1) {
+    const int sbits = a.swapped ? a.mb : a.nb, bbits = a.swapped ? a.nb : a.mb;
+    if (!generic_rows_fit(a.kb, sbits, bbits))
+      throw std::runtime_error("row-streaming form launched on a node it does not fit");
+    const int lu = sbits >= 8 + kRowsLog2U ? kRowsLog2U : 0;
+    const int64_t items = a.nvar << (sbits - 8 - lu);
+    const int grid = int(std::min<int64_t>(items, a.amax_out ? 4096 : (int64_t(1) << 20)));
+#define XEB_ROWS_CASE(KB)                                                                   \
+  case KB:                                                                                 \
+    if (lu)                                                                                \
+      launch(k_contract_rows<KB, 1 << kRowsLog2U>, dim3(grid), dim3(256), s, true, true, a); \
+    else                                                                                   \
+      launch(k_contract_rows<KB, 1>, dim3(grid), dim3(256), s, true, true, a);              \
+    break;
+    switch (a.kb) {
+      XEB_ROWS_CASE(0)
+      XEB_ROWS_CASE(1)
+      XEB_ROWS_CASE(2)
+      XEB_ROWS_CASE(3)
+      XEB_ROWS_CASE(4)
+      default: break;
+    }
+#undef XEB_ROWS_CASE
+    return;
+  }
   // Tracking the FP16 scale costs one atomic per workgroup: keep the grid at
   // a few workgroups per CU then (grid-stride loop).  With a key spanning
   // whole 256-element chunks a workgroup takes one chunk per step.

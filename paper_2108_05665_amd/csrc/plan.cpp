@@ -171,13 +171,30 @@ void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb,
   nb.keyed = nb.pair_mode == 2 ? 1 : 0;
 }
 
-void configure_generic(NodeBlock& nb) {
+void configure_generic(NodeBlock& nb, int form, int stream_l) {
   nb.kernel = XEB_KERNEL_GENERIC;
   nb.keyed = 0;
-  nb.tile = 0;
-  nb.swapped = 0;
+  nb.tile = form;
+  nb.swapped = form == 1 ? stream_l : 0;
   nb.ksplit = 1;
   nb.pair_mode = 0;
+}
+
+bool generic_rows_ok(const Node& nd, int stream_l) {
+  return stream_l ? generic_rows_fit(nd.kb, nd.mb, nd.nb) : generic_rows_fit(nd.kb, nd.nb, nd.mb);
+}
+
+void configure_generic_default(const Node& nd, NodeBlock& nb) {
+  // The row-streaming form where it fits, streaming the wider side.
+  const int first = nd.mb > nd.nb ? 1 : 0;
+  for (int i = 0; i < 2; ++i) {
+    const int sl = i == 0 ? first : 1 - first;
+    if (generic_rows_ok(nd, sl)) {
+      configure_generic(nb, 1, sl);
+      return;
+    }
+  }
+  configure_generic(nb, 0, 0);
 }
 
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped) {
@@ -209,7 +226,7 @@ void choose_kernel(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, 
     for (int64_t v = 0; v < nb.nvar; ++v)
       nb.pairs[size_t(int64_t(nb.lidx[v]) * nvarR + nb.ridx[v])] = int32_t(v);
   }
-  configure_generic(nb);
+  configure_generic_default(nd, nb);
   if (force_generic) return;
   if (mfma_keyed(nd, nvarL, nvarR, nb)) {
     // One GEMM per key: the largest tile that each key's block fills, the
@@ -1015,7 +1032,9 @@ ContractArgs node_args(Plan* p, const Block& blk, int T, int64_t sigma) {
   a.nb = sw ? nd.mb : nd.nb;
   a.kb = nd.kb;
   a.pair_mode = nb.pair_mode;
-  a.swapped = sw ? 1 : 0;
+  // (The per-element kernel keeps L and R in place; its swapped flag names
+  // the stream side of the row-streaming form.)
+  a.swapped = nb.kernel == XEB_KERNEL_MFMA ? (sw ? 1 : 0) : nb.swapped;
   a.tile = nb.tile;
   a.tk = nb.tk;
   a.kg = nb.kg;

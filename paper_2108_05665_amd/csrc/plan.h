@@ -164,7 +164,13 @@ bool mfma_can_run(const Node& nd, int64_t nvarL, int64_t nvarR, const NodeBlock&
                   int swapped, int ksplit, int keyed = 0);
 void configure_mfma(const Node& nd, int64_t nvarL, int64_t nvarR, NodeBlock& nb, int tile, int swapped,
                     int ksplit, int tk, int kg = 1, int keyed = 0);
-void configure_generic(NodeBlock& nb);
+// The per-element kernel: form 0 one thread per output element, form 1 the
+// row-streaming form (stream_l: stream L's rows rather than R's).
+void configure_generic(NodeBlock& nb, int form, int stream_l);
+// Whether the row-streaming form fits the node with that stream side.
+bool generic_rows_ok(const Node& nd, int stream_l);
+// The row-streaming form where it fits (the wider side streamed), else form 0.
+void configure_generic_default(const Node& nd, NodeBlock& nb);
 int64_t node_tiles(const Node& nd, int64_t nvarL, int64_t nvarR, int tile, int swapped);
 // Key count of node `id` in block `blk` (a leaf's: all its keys).
 int64_t nvar_in(const Plan* p, const Block& blk, int id);

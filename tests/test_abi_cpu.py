@@ -315,6 +315,51 @@ def test_node_config_get_set_and_validation():
         p.node_config(leaf)
 
 
+def test_generic_row_streaming_form_config():
+    """The per-element kernel's row-streaming form: chosen by default where
+    the shape fits (K <= 16, a side of >= 8 bits streamed, the other side
+    <= 6 bits; the wider side streamed), switchable per node in both
+    directions, and rejected on shapes it does not fit."""
+    c = grid_circuit(4, 6, 12, seed=77)
+    s = prefix_bitstrings(24, 4000, 16, 5)
+    ch, sl, _ = planner.plan(c, s, n_sliced=3, trials=6)
+    p = xeb.Plan(c, s, ch, sl, bind=False, force_generic=True)
+
+    def fits(ns, side):
+        stream, other = (ns["m_bits"], ns["n_bits"]) if side else (ns["n_bits"], ns["m_bits"])
+        return ns["k_bits"] <= 4 and stream >= 8 and other <= 6
+
+    stats = p.all_node_stats()
+    rows = [ns for ns in stats if ns["tile"] == -2]
+    assert rows
+    for ns in stats:
+        assert ns["kernel"] == "generic"
+        if fits(ns, 0) or fits(ns, 1):
+            assert ns["tile"] == -2
+            wide = 1 if ns["m_bits"] > ns["n_bits"] else 0
+            assert ns["swapped"] == (wide if fits(ns, wide) else 1 - wide)
+        else:
+            assert (ns["tile"], ns["swapped"]) == (-1, 0)
+    node = rows[0]["node"]
+    assert p.node_config(node)["tile"] == -2
+    p.set_node_config(node, "generic", tile=-1)
+    assert (p.node_config(node)["tile"], p.node_config(node)["swapped"]) == (-1, 0)
+    p.set_node_config(node, "generic", tile=-2, swapped=rows[0]["swapped"])
+    assert p.node_config(node) == dict(kernel="generic", tile=-2, swapped=rows[0]["swapped"],
+                                       ksplit=1, k_slab=0, k_groups=1, keyed=0)
+    unfit = [ns for ns in stats if not fits(ns, 0) and not fits(ns, 1)]
+    assert unfit
+    for ns in unfit[:5]:
+        for side in (0, 1):
+            with pytest.raises(xeb.XebError) as e:
+                p.set_node_config(ns["node"], "generic", tile=-2, swapped=side)
+            assert e.value.code == xeb.XEB_EINVAL
+            assert p.node_config(ns["node"])["tile"] == -1
+    with pytest.raises(xeb.XebError) as e:
+        p.set_node_config(node, "generic", tile=-2, swapped=2)
+    assert e.value.code == xeb.XEB_EINVAL
+
+
 def test_batch_grouping_under_the_graph_limit():
     """BatchSet's grouping: consecutive plans, every plan in exactly one group,
     no group of two or more above 90 % of the node limit, and the launch
