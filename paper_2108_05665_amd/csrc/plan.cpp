@@ -881,12 +881,30 @@ void compile_plan(Plan& p, const xeb_circuit_t* c, const uint64_t* bits, int64_t
       int run_m = 0, run_n = 0;
       while (run_m < nd.mb && nd.posM[run_m] == run_m) ++run_m;
       while (run_n < nd.nb && nd.posN[run_n] == run_n) ++run_n;
+      // 128 x 128 output tiles of the stacked (left rows x right rows)
+      // product, and those holding at least one key.
+      const int64_t nl = p.nodes[nd.left].leaf ? p.nodes[nd.left].leaf_nvar : blk.nodes[nd.left - L].nvar;
+      const int64_t nr = p.nodes[nd.right].leaf ? p.nodes[nd.right].leaf_nvar : blk.nodes[nd.right - L].nvar;
+      const int64_t tr = ((nl << nd.mb) + 127) / 128, tc = ((nr << nd.nb) + 127) / 128;
+      std::vector<uint8_t> hit;
+      int64_t used = 0;
+      if (tr * tc <= (int64_t(1) << 26)) {
+        hit.assign(size_t(tr * tc), 0);
+        for (int64_t v = 0; v < nb.nvar; ++v) {
+          const int64_t r0 = (int64_t(nb.lidx[v]) << nd.mb) / 128, r1 = ((int64_t(nb.lidx[v] + 1) << nd.mb) - 1) / 128;
+          const int64_t c0 = (int64_t(nb.ridx[v]) << nd.nb) / 128, c1 = ((int64_t(nb.ridx[v] + 1) << nd.nb) - 1) / 128;
+          for (int64_t r = r0; r <= r1; ++r)
+            for (int64_t c = c0; c <= c1; ++c) hit[size_t(r * tc + c)] = 1;
+        }
+        for (uint8_t h : hit) used += h;
+      }
       std::fprintf(stderr,
                    "{\"node\":%d,\"left\":%d,\"right\":%d,\"variants\":%lld,\"m_bits\":%d,"
                    "\"n_bits\":%d,\"k_bits\":%d,\"slice_mask\":%llu,\"kernel\":%d,\"blocks\":%zu,"
-                   "\"low_run_m\":%d,\"low_run_n\":%d}\n",
+                   "\"low_run_m\":%d,\"low_run_n\":%d,\"tiles_128\":%lld,\"key_tiles_128\":%lld}\n",
                    T, nd.left, nd.right, (long long)nb.nvar, nd.mb, nd.nb, nd.kb,
-                   (unsigned long long)nd.smask, nb.kernel, p.blocks.size(), run_m, run_n);
+                   (unsigned long long)nd.smask, nb.kernel, p.blocks.size(), run_m, run_n,
+                   (long long)(tr * tc), (long long)used);
     }
   }
 }
