@@ -73,10 +73,13 @@ def test_rows_form_vs_state_vector_and_per_element_form():
     assert _rel(a_rows, a_elem) <= FORM_TOL
 
 
-def test_rows_form_scale_feeds_split_fp16_mfma_nodes():
+@pytest.mark.parametrize("precision", ["split_fp16", "split_bf16"])
+def test_rows_form_feeds_split_mfma_nodes(precision):
+    """Row-streaming nodes whose tables MFMA nodes consume (for FP16, through
+    the largest magnitude the row-streaming kernel publishes for the scale)."""
     circ, strings, ch, sl = _case24()
     ref = statevec.state_vector(circ)[strings.astype(np.int64)]
-    p = xeb.Plan(circ, strings, ch, sl, precision="split_fp16", mfma_min_cmacs=65536.0)
+    p = xeb.Plan(circ, strings, ch, sl, precision=precision, mfma_min_cmacs=65536.0)
     assert _rows_nodes(p)
     assert any(ns["kernel"] == "mfma" for ns in p.all_node_stats())
     assert _rel(_amps(p), ref) <= SPLIT_TOL

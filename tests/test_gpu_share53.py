@@ -5,11 +5,17 @@ first strings against the stored FP64 oracle values
 (tests/golden/share_53q_m14_partials.json, written by
 tests/golden/make_share53_partials.py from the oracle alone).  A partial
 slice block yields no amplitude (Appendix A, "Slicing"), so the partials are
-what is compared.  Bounds as for the other workloads: complex64 1e-5, split
-forms 1e-3 normwise.
+what is compared.  Split forms 1e-3 normwise.  complex64: each internal
+node's element is a sum of K = 2^k FP32 products, whose rounding error for
+random-phase terms is about u sqrt(K) relative (u = 2^-24); independent
+per-node errors add in quadrature on their way to the root, so the partials
+carry about u sqrt(sum over nodes of 2^k) (2.3e-5 for this tree, against 5.7e-6
+for the 36-qubit workload's tree, whose measured error is 2.7e-6).  The bound
+is twice that estimate, and never below the 1e-5 of the shallower workloads.
 """
 
 import json
+import math
 import os
 
 import numpy as np
@@ -27,6 +33,12 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "share_53q_m14_partials.json")
 TOL = {"c64": 1e-5, "split_fp16": 1e-3, "split_bf16": 1e-3}
 
 
+def fp32_depth_estimate(p):
+    """u sqrt(sum over internal nodes of 2^k): the expected relative FP32
+    accumulation error of the root's partials."""
+    return 2.0 ** -24 * math.sqrt(sum(2.0 ** ns["k_bits"] for ns in p.all_node_stats()))
+
+
 @pytest.mark.parametrize("precision", ["split_fp16", "c64"])
 def test_share53_slice_partials_vs_oracle(precision):
     with open(PLAN) as f:
@@ -42,6 +54,11 @@ def test_share53_slice_partials_vs_oracle(precision):
     p = xeb.Plan(circ, strings, fx["children"], fx["sliced"], precision=precision,
                  memory_budget=270 * 2**30)
     assert p.stats()["n_sliced"] == len(fx["sliced"])
+    tol = TOL[precision]
+    if precision == "c64":
+        est = fp32_depth_estimate(p)
+        assert 1e-5 < est < 1e-4
+        tol = max(tol, 2 * est)
     for sigma in gold["sigmas"]:
         a = p.new_amps()
         p.contract(a, sigma, sigma + 1)
@@ -49,8 +66,8 @@ def test_share53_slice_partials_vs_oracle(precision):
         got = a[: gold["n_strings"]].cpu().numpy()
         ref = np.array([complex(*x["partial"]) for x in gold["partials"] if x["sigma"] == sigma])
         rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        print(f"{precision} slice {sigma}: normwise {rel:.2e}")
-        assert rel <= TOL[precision], (sigma, rel)
+        print(f"{precision} slice {sigma}: normwise {rel:.2e} (bound {tol:.2e})")
+        assert rel <= tol, (sigma, rel)
         del a
     p.close()
     torch.cuda.empty_cache()
