@@ -58,11 +58,10 @@ std::vector<Candidate> candidates(const Plan* p, const Node& nd, int64_t nl, int
   const double useful = double(nb.nvar) * std::ldexp(1.0, nd.mb + nd.nb + nd.kb);
   // The per-element kernel cannot win on large contractions; leave those out
   // to bound the tuning time.
-  if (useful <= std::ldexp(1.0, 30)) {
-    out.push_back(kGeneric);
-    for (int sl = 0; sl < 2; ++sl)
-      if (generic_rows_ok(nd, sl)) out.push_back(generic_rows(sl));
-  }
+  if (useful <= std::ldexp(1.0, 30)) out.push_back(kGeneric);
+  // (The row-streaming form is HBM-bound at any size.)
+  for (int sl = 0; sl < 2; ++sl)
+    if (generic_rows_ok(nd, sl)) out.push_back(generic_rows(sl));
   const int64_t K = int64_t(1) << nd.kb;
   // Keyed form: the only MFMA form of a node too sparse to stack, and an
   // alternative to the pair table (which multiplies up to 8x the useful

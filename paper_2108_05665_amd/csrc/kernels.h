@@ -92,8 +92,10 @@ void take_launch_events(hipEvent_t* start, hipEvent_t* stop);
 // streams L's), for the shapes generic_rows_fit accepts.
 void launch_contract_generic(const ContractArgs& a, hipStream_t s);
 // Stream rows per thread in the row-streaming form (log2), where the stream
-// side has at least 8 + kRowsLog2U bits (one row per thread below that).
+// side has at least 8 + kRowsLog2U bits and that leaves at least
+// kRowsMinItems work items (one row per thread otherwise).
 constexpr int kRowsLog2U = 2;
+constexpr int64_t kRowsMinItems = 2048;
 // The row-streaming form runs K = 2^kb <= 16, a stream side of at least 8
 // bits (256 rows per work item) and at most 64 broadcast rows.
 inline bool generic_rows_fit(int kb, int stream_bits, int bcast_bits) {
